@@ -1,0 +1,444 @@
+/*
+ * FP64 CPU oracle of the two-range pseudopotential lattice Boltzmann step
+ * for a binary mixture with per-component relaxation times
+ * (Fei, Scagliarini, Montessori, Lauricella, Succi, Luo,
+ *  "Mesoscopic model for soft flowing systems with tunable viscosity ratio",
+ *  arXiv:1806.06943, Sec. II).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the HIP path is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header, table or constant with the HIP library: every
+ * weight below is typed here from the paper.
+ *
+ * Layout (all double precision, row-major, x fastest):
+ *   f   [k][i][y][x]   k in {A=0,B=1}, i in 0..8 (D2Q9)
+ *   rho [k][y][x]
+ *   F   [k][d][y][x]   d in {x=0,y=1}
+ *
+ * D2Q9 ordering (the paper's Fig. 1 is not available; any consistent order
+ * gives identical results):
+ *   0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)
+ *
+ * Readings of points the paper leaves open (each is listed with its reason
+ * in the design notes of the repository):
+ *   - equilibrium carries the usual factor 1/2 on the quadratic term
+ *     (Eq. 2 as printed omits it; without it the second moment is wrong);
+ *   - within a step: densities -> pseudopotential -> forces -> moments with
+ *     F/2 -> common velocity -> BGK + Guo collision -> streaming;
+ *   - the mid-range sum of Eq. 8 runs over all 25 vectors of D2Q25 (both
+ *     belts), exactly as the equation is written;
+ *   - body force F^b_k = rho_k g_k (g an acceleration per component);
+ *   - walls (walls=1): x periodic, half-way bounce-back half a link below
+ *     row 0 and above row ny-1; the force stencil sees virtual densities
+ *     rho_wall[k] at rows outside the fluid.
+ *
+ * Parity pins: lattice moment sums, equilibrium/forcing moments, a
+ * sinusoidal closed form of both stencils, an exact-rational brute force on
+ * a 4x4 torus, mass and momentum identities, Laplace's law and the
+ * two-component Poiseuille profile (Eq. 19) are checked by the tests.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int nx, ny, walls;
+    double G_AB;        /* Eq. 9 inter-species coupling (>0 repulsive)   */
+    double G1[2];       /* Eq. 8 short-range coupling per component       */
+    double G2[2];       /* Eq. 8 mid-range coupling per component         */
+    double tau[2];      /* Eq. 1 relaxation time per component            */
+    double rho0;        /* pseudopotential reference density (Sec. II B)  */
+    double g[2][2];     /* body acceleration per component, (x, y)        */
+    double rho_wall[2]; /* virtual densities beyond the walls             */
+} ora_params;
+
+/* ---- lattice tables, typed from Sec. II A (D2Q9) and Sec. II B (D2Q25) ---- */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double CS2 = 1.0 / 3.0;
+
+/* w(|e|^2): w(0)=4/9, w(1)=1/9, w(2)=1/36 (Eq. 2) */
+static double w_of(int e2)
+{
+    switch (e2) {
+    case 0: return 4.0 / 9.0;
+    case 1: return 1.0 / 9.0;
+    case 2: return 1.0 / 36.0;
+    }
+    return 0.0;
+}
+
+/* p(|e|^2) for D2Q25 (Eq. 8): p(0)=247/420, p(1)=4/63, p(2)=4/135,
+ * p(4)=1/180, p(5)=2/945, p(8)=1/15120; zero for every other |e|^2. */
+static double p_of(int e2)
+{
+    switch (e2) {
+    case 0: return 247.0 / 420.0;
+    case 1: return 4.0 / 63.0;
+    case 2: return 4.0 / 135.0;
+    case 4: return 1.0 / 180.0;
+    case 5: return 2.0 / 945.0;
+    case 8: return 1.0 / 15120.0;
+    }
+    return 0.0;
+}
+
+static double wi(int i) { return w_of(EX[i] * EX[i] + EY[i] * EY[i]); }
+
+/* Exported copy of the tables so that tests can check them against the
+ * paper's numbers and the isotropy sums.  D2Q25 order: dy outer, dx inner,
+ * both from -2 to 2. */
+void ora_tables(int *ex9, int *ey9, int *opp9, double *w9,
+                int *ex25, int *ey25, double *p25)
+{
+    for (int i = 0; i < 9; ++i) {
+        ex9[i] = EX[i];
+        ey9[i] = EY[i];
+        opp9[i] = OPP[i];
+        w9[i] = wi(i);
+    }
+    int j = 0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            ex25[j] = dx;
+            ey25[j] = dy;
+            p25[j] = p_of(dx * dx + dy * dy);
+            ++j;
+        }
+}
+
+/* ---- indexing helpers ---- */
+static int wrap(int a, int n)
+{
+    if (a >= 0 && a < n) return a;
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+static size_t NODE(const ora_params *p, int x, int y)
+{
+    return (size_t)y * p->nx + x;
+}
+
+static size_t FIDX(const ora_params *p, int k, int i, int x, int y)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    return ((size_t)k * 9 + i) * N + NODE(p, x, y);
+}
+
+/* pseudopotential psi(rho) = rho0 (1 - exp(-rho/rho0)) (Sec. II B) */
+static double psi_of(const ora_params *p, double rho)
+{
+    return p->rho0 * (1.0 - exp(-rho / p->rho0));
+}
+
+/* Source of densities for the force stencil: precomputed density and
+ * pseudopotential arrays (rho != NULL), or, when rho is NULL, sums of the
+ * populations taken on demand (used to step a single node of a large
+ * lattice). */
+typedef struct {
+    const double *rho;
+    const double *psi;
+    const double *f;
+} dens_src;
+
+/* Density of component k seen at (x, y): periodic in x; periodic in y
+ * without walls, the virtual wall density beyond the walls. */
+static double rho_at(const ora_params *p, const dens_src *s, int k, int x, int y)
+{
+    x = wrap(x, p->nx);
+    if (p->walls) {
+        if (y < 0 || y >= p->ny) return p->rho_wall[k];
+    } else {
+        y = wrap(y, p->ny);
+    }
+    if (s->rho) return s->rho[(size_t)k * p->nx * p->ny + NODE(p, x, y)];
+    double r = 0.0;
+    for (int i = 0; i < 9; ++i) r += s->f[FIDX(p, k, i, x, y)];
+    return r;
+}
+
+/* Pseudopotential of component k seen at (x, y), same wrapping rules. */
+static double psi_at(const ora_params *p, const dens_src *s, int k, int x, int y)
+{
+    if (!s->psi) return psi_of(p, rho_at(p, s, k, x, y));
+    x = wrap(x, p->nx);
+    if (p->walls) {
+        if (y < 0 || y >= p->ny) return psi_of(p, p->rho_wall[k]);
+    } else {
+        y = wrap(y, p->ny);
+    }
+    return s->psi[(size_t)k * p->nx * p->ny + NODE(p, x, y)];
+}
+
+/* psi[k][y][x] from rho[k][y][x] */
+static void psi_field(const ora_params *p, const double *rho, double *psi)
+{
+    size_t n2 = 2 * (size_t)p->nx * p->ny;
+    for (size_t n = 0; n < n2; ++n) psi[n] = psi_of(p, rho[n]);
+}
+
+/* ---- Eq. 6: component densities ---- */
+void ora_density(const ora_params *p, const double *f, double *rho)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    for (int k = 0; k < 2; ++k)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                double s = 0.0;
+                for (int i = 0; i < 9; ++i) s += f[FIDX(p, k, i, x, y)];
+                rho[(size_t)k * N + NODE(p, x, y)] = s;
+            }
+}
+
+/* ---- Eqs. 8, 9 and the body force: total force on component k at one node ---- */
+static void force_at(const ora_params *p, const dens_src *rho, int k, int x, int y,
+                     double *Fx, double *Fy)
+{
+    int kb = 1 - k;
+    double psi_x = psi_at(p, rho, k, x, y);
+    double rho_x = rho_at(p, rho, k, x, y);
+
+    /* short-range attraction within k: sum over D2Q9 with weights w */
+    double s1x = 0.0, s1y = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        double ps = psi_at(p, rho, k, x + EX[i], y + EY[i]);
+        s1x += wi(i) * ps * EX[i];
+        s1y += wi(i) * ps * EY[i];
+    }
+    /* mid-range repulsion within k: sum over all of D2Q25 with weights p */
+    double s2x = 0.0, s2y = 0.0;
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            double ps = psi_at(p, rho, k, x + dx, y + dy);
+            double pw = p_of(dx * dx + dy * dy);
+            s2x += pw * ps * dx;
+            s2y += pw * ps * dy;
+        }
+    /* inter-species repulsion: density (not psi) of the other component */
+    double srx = 0.0, sry = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        double rb = rho_at(p, rho, kb, x + EX[i], y + EY[i]);
+        srx += wi(i) * rb * EX[i];
+        sry += wi(i) * rb * EY[i];
+    }
+    *Fx = -p->G1[k] * psi_x * s1x - p->G2[k] * psi_x * s2x - p->G_AB * rho_x * srx
+          + rho_x * p->g[k][0];
+    *Fy = -p->G1[k] * psi_x * s1y - p->G2[k] * psi_x * s2y - p->G_AB * rho_x * sry
+          + rho_x * p->g[k][1];
+}
+
+void ora_forces(const ora_params *p, const double *rho_arr, double *F)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *psi = (double *)malloc(2 * N * sizeof(double));
+    psi_field(p, rho_arr, psi);
+    dens_src rho = {rho_arr, psi, NULL};
+    for (int k = 0; k < 2; ++k)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                double fx, fy;
+                force_at(p, &rho, k, x, y, &fx, &fy);
+                F[((size_t)k * 2 + 0) * N + NODE(p, x, y)] = fx;
+                F[((size_t)k * 2 + 1) * N + NODE(p, x, y)] = fy;
+            }
+    free(psi);
+}
+
+/* ---- Eq. 2 with the 1/2 on the quadratic term ---- */
+static double feq_i(int i, double rho, double ux, double uy)
+{
+    double eu = EX[i] * ux + EY[i] * uy;
+    double uu = ux * ux + uy * uy;
+    return wi(i) * rho * (1.0 + eu / CS2 + (eu * eu - CS2 * uu) / (2.0 * CS2 * CS2));
+}
+
+void ora_feq(double rho, double ux, double uy, double *out9)
+{
+    for (int i = 0; i < 9; ++i) out9[i] = feq_i(i, rho, ux, uy);
+}
+
+/* ---- Eq. 5: Guo forcing term evaluated with the common velocity ---- */
+static double guo_i(int i, double tau, double ux, double uy, double Fx, double Fy)
+{
+    double eu = EX[i] * ux + EY[i] * uy;
+    double cx = (EX[i] - ux) / CS2 + eu * EX[i] / (CS2 * CS2);
+    double cy = (EY[i] - uy) / CS2 + eu * EY[i] / (CS2 * CS2);
+    return (1.0 - 1.0 / (2.0 * tau)) * wi(i) * (cx * Fx + cy * Fy);
+}
+
+void ora_guo(double tau, double ux, double uy, double Fx, double Fy, double *out9)
+{
+    for (int i = 0; i < 9; ++i) out9[i] = guo_i(i, tau, ux, uy, Fx, Fy);
+}
+
+/* ---- Eqs. 6 and 3: moments with F/2 and the common velocity at a node ---- */
+typedef struct {
+    double rho[2], jx[2], jy[2], Fx[2], Fy[2], ux, uy;
+} node_macro;
+
+static void macro_at(const ora_params *p, const double *f, const dens_src *rho, int x,
+                     int y, node_macro *m)
+{
+    double numx = 0.0, numy = 0.0, den = 0.0;
+    for (int k = 0; k < 2; ++k) {
+        double mx = 0.0, my = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double fi = f[FIDX(p, k, i, x, y)];
+            mx += fi * EX[i];
+            my += fi * EY[i];
+        }
+        m->rho[k] = rho_at(p, rho, k, x, y);
+        force_at(p, rho, k, x, y, &m->Fx[k], &m->Fy[k]);
+        m->jx[k] = mx + 0.5 * m->Fx[k];
+        m->jy[k] = my + 0.5 * m->Fy[k];
+        numx += m->jx[k] / p->tau[k];
+        numy += m->jy[k] / p->tau[k];
+        den += m->rho[k] / p->tau[k];
+    }
+    m->ux = numx / den;
+    m->uy = numy / den;
+}
+
+/* ---- Eq. 1 right-hand side: post-collision value of f_{k,i} at a node ---- */
+static double post_collision(const ora_params *p, const double *f, const node_macro *m,
+                             int k, int i, int x, int y)
+{
+    double fi = f[FIDX(p, k, i, x, y)];
+    double tau = p->tau[k];
+    double eq = feq_i(i, m->rho[k], m->ux, m->uy);
+    double c = guo_i(i, tau, m->ux, m->uy, m->Fx[k], m->Fy[k]);
+    return fi - (fi - eq) / tau + c;
+}
+
+/* ---- one full time step: fnew = stream(collide(f)) ----
+ * work must hold 4*nx*ny doubles (densities and pseudopotentials). */
+void ora_step(const ora_params *p, const double *f, double *fnew, double *work)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    ora_density(p, f, work);
+    psi_field(p, work, work + 2 * N);
+    dens_src rho = {work, work + 2 * N, NULL};
+    #pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            node_macro m;
+            macro_at(p, f, &rho, x, y, &m);
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 9; ++i) {
+                    double fs = post_collision(p, f, &m, k, i, x, y);
+                    int xd = wrap(x + EX[i], p->nx);
+                    int yd = y + EY[i];
+                    if (p->walls && (yd < 0 || yd >= p->ny)) {
+                        /* half-way bounce-back: returns to the same node reversed */
+                        fnew[FIDX(p, k, OPP[i], x, y)] = fs;
+                    } else {
+                        yd = wrap(yd, p->ny);
+                        fnew[FIDX(p, k, i, xd, yd)] = fs;
+                    }
+                }
+        }
+}
+
+/* Advance f in place by nsteps.  work must hold 22*nx*ny doubles. */
+void ora_run(const ora_params *p, double *f, long nsteps, double *work)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *tmp = work;
+    double *rho = work + 18 * N;
+    for (long s = 0; s < nsteps; ++s) {
+        ora_step(p, f, tmp, rho);
+        memcpy(f, tmp, 18 * N * sizeof(double));
+    }
+}
+
+/* Next-step populations of one node (x, y), in the pull form of the same
+ * update: f_{k,i}(x, t+1) is the post-collision value at x - e_i, or, when
+ * x - e_i lies beyond a wall, the reversed post-collision value of x itself.
+ * Densities are summed on demand, so only the neighbourhood of (x, y) is
+ * touched: used to check sampled nodes of lattices too large to step whole.
+ * out18 = [k][i]. */
+void ora_step_at(const ora_params *p, const double *f, int x, int y, double *out18)
+{
+    dens_src rho = {NULL, NULL, f};
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i) {
+            int sx = x - EX[i], sy = y - EY[i], ii = i;
+            if (p->walls && (sy < 0 || sy >= p->ny)) {
+                sx = x;
+                sy = y;
+                ii = OPP[i];
+            }
+            sx = wrap(sx, p->nx);
+            sy = wrap(sy, p->ny);
+            node_macro m;
+            macro_at(p, f, &rho, sx, sy, &m);
+            out18[k * 9 + i] = post_collision(p, f, &m, k, ii, sx, sy);
+        }
+}
+
+/* ---- initial state: equilibrium at rest from given densities (reading) ---- */
+void ora_init(const ora_params *p, const double *rhoA, const double *rhoB, double *f)
+{
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                f[FIDX(p, 0, i, x, y)] = wi(i) * rhoA[NODE(p, x, y)];
+                f[FIDX(p, 1, i, x, y)] = wi(i) * rhoB[NODE(p, x, y)];
+            }
+}
+
+/* ---- macroscopic fields for observables ----
+ * rho[k][y][x], j[k][d][y][x] (component momentum with F/2, Eq. 6),
+ * F[k][d][y][x], ueq[d][y][x] (Eq. 3), u[d][y][x] (barycentric, Eq. 7),
+ * pb[y][x] (bulk equation of state, Eq. 11).  Any output may be NULL. */
+void ora_fields(const ora_params *p, const double *f, double *rho_out, double *j_out,
+                double *F_out, double *ueq_out, double *u_out, double *pb_out)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *rho_arr = (double *)malloc(2 * N * sizeof(double));
+    double *psi = (double *)malloc(2 * N * sizeof(double));
+    ora_density(p, f, rho_arr);
+    psi_field(p, rho_arr, psi);
+    dens_src rho = {rho_arr, psi, NULL};
+    #pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            node_macro m;
+            macro_at(p, f, &rho, x, y, &m);
+            size_t n = NODE(p, x, y);
+            double rt = m.rho[0] + m.rho[1];
+            for (int k = 0; k < 2; ++k) {
+                if (rho_out) rho_out[k * N + n] = m.rho[k];
+                if (j_out) {
+                    j_out[(k * 2 + 0) * N + n] = m.jx[k];
+                    j_out[(k * 2 + 1) * N + n] = m.jy[k];
+                }
+                if (F_out) {
+                    F_out[(k * 2 + 0) * N + n] = m.Fx[k];
+                    F_out[(k * 2 + 1) * N + n] = m.Fy[k];
+                }
+            }
+            if (ueq_out) {
+                ueq_out[n] = m.ux;
+                ueq_out[N + n] = m.uy;
+            }
+            if (u_out) {
+                u_out[n] = (m.jx[0] + m.jx[1]) / rt;
+                u_out[N + n] = (m.jy[0] + m.jy[1]) / rt;
+            }
+            if (pb_out) {
+                double s = 0.0;
+                for (int k = 0; k < 2; ++k) {
+                    double ps = psi_of(p, m.rho[k]);
+                    s += (m.rho[k] + 0.5 * (p->G1[k] + p->G2[k]) * ps * ps) * CS2;
+                }
+                s += p->G_AB * m.rho[0] * m.rho[1] * CS2;
+                pb_out[n] = s;
+            }
+        }
+    free(rho_arr);
+    free(psi);
+}
