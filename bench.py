@@ -1,0 +1,165 @@
+"""Benchmark of the two-component D2Q9 two-range pseudopotential LBM step on one MI355X.
+
+Workload: spinodal decomposition on a 2048 x 2048 periodic lattice,
+rho_A = 0.5 + U(-0.05, 0.05) per node (seeded), rho_B = 1 - rho_A,
+couplings (G_AB, G_1, G_2) = (0.405, -9.0, 8.1), tau = (1.0, 0.55), FP32 arithmetic
+and storage.  One step advances both components of every node (one lattice
+update, LU); the timed region replays the captured step loop with the inputs
+resident in HBM, plus one FP64 observable pass (mass and finiteness guard)
+per 1000 steps.
+
+Prints ONE JSON line with MLUPS, the HBM roofline of the dominant kernel
+(HIP-event timing on the context's stream), a measured copy-kernel ceiling
+and the CPU oracle's rate on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, public figure
+B_PER_LU_STEP_KERNEL = 152.0    # k_step: read 18 + write 18 FP32 populations, read 2 densities
+B_PER_LU_DENSITY_KERNEL = 80.0  # k_density: read 18 populations, write 2 densities
+B_PER_LU_IDEAL = 160.0          # single-pass minimum: populations R+W, densities W+R
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--nx", type=int, default=2048)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~15 s)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, budget_s=15.0, steps=0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle as O
+    p = O.Params(nx=w.nx, ny=w.ny, G_AB=w.G_AB, G1=w.G1, G2=w.G2, tau=w.tau)
+    f = O.init(p, w.rhoA, w.rhoB)
+    t0 = time.perf_counter()
+    f = O.run(p, f, 1)
+    t1 = time.perf_counter() - t0
+    n = steps if steps > 0 else max(1, min(50, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(p, f, n)
+    dt = time.perf_counter() - t0
+    return {"value": w.nx * w.ny * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the {w.nx}x{w.ny} spinodal workload, FP64, "
+                      f"OpenMP over rows ({dt:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU path is "
+              "design-only in this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1806_06943_amd import lbm
+    from paper_1806_06943_amd import workloads as W
+
+    w = W.spinodal(nx=a.nx, ny=a.ny)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sim = lbm.Sim([lbm.workload_instance(w)], device="cuda:0")
+    N = w.nx * w.ny
+
+    # warm-up (captures the step graph)
+    sim.step(a.warmup)
+    obs0, _ = sim.observables()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, observables every 1000 steps
+    st = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(st)
+    done = 0
+    while done < a.steps:
+        n = min(1000, a.steps - done)
+        sim.step(n)
+        done += n
+        if done % 1000 == 0 or done == a.steps:
+            sim.observables()
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / a.steps
+    mlups = N * a.steps / (ms_total * 1e-3) / 1e6
+    obs1, _ = sim.observables()
+
+    # per-kernel durations on the context's stream (HIP events)
+    prof = dict(lbm.lbm_profile_step(sim.ctx, 50))
+    k_ms = prof["k_step"]
+    achieved = B_PER_LU_STEP_KERNEL * N / (k_ms * 1e-3) / 1e9
+
+    # achievable HBM bandwidth: the library's copy kernel over 2 x 1 GiB
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    lbm.lbm_copy_probe(sim.ctx, dst.data_ptr(), src.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(st)
+    reps = 20
+    for _ in range(reps):
+        lbm.lbm_copy_probe(sim.ctx, dst.data_ptr(), src.data_ptr(), nbytes)
+    c1.record(st)
+    torch.cuda.synchronize()
+    copy_gbps = 2 * nbytes * reps / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
+    cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
+
+    mass_drift = [abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] for k in range(2)]
+    out = {
+        "metric": "MLUPS (2-comp)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"spinodal {w.nx}x{w.ny} periodic, D2Q9 two-component two-range "
+                               "pseudopotential (G_AB=0.405, G1=-9.0, G2=8.1, tau=(1.0, 0.55))",
+                   "nx": w.nx, "ny": w.ny, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_step", "bytes_per_lu": B_PER_LU_STEP_KERNEL,
+                     "kernel_ms": round(k_ms, 5)},
+        "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
+        "alg_gbps_at_160B_per_LU": round(mlups * 1e6 * B_PER_LU_IDEAL / 1e9, 1),
+        "copy_kernel_gbps": round(copy_gbps, 1),
+        "frac_of_copy_ceiling_at_160B": round(mlups * 1e6 * B_PER_LU_IDEAL / 1e9 / copy_gbps, 4),
+        "mass_drift_fp32": mass_drift,
+        "wall_s": round(wall, 3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -41,6 +41,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int nx, ny, walls;
@@ -52,6 +55,16 @@ typedef struct {
     double g[2][2];     /* body acceleration per component, (x, y)        */
     double rho_wall[2]; /* virtual densities beyond the walls             */
 } ora_params;
+
+/* number of OpenMP threads the row loops use (1 without OpenMP) */
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ---- lattice tables, typed from Sec. II A (D2Q9) and Sec. II B (D2Q25) ---- */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};

@@ -88,11 +88,17 @@ def lib():
         L.ora_step_at.argtypes = [P, _D, ctypes.c_int, ctypes.c_int, _D]
         L.ora_init.argtypes = [P, _D, _D, _D]
         L.ora_fields.argtypes = [P, _D, _D, _D, _D, _D, _D, _D]
+        L.ora_threads.restype = ctypes.c_int
         if hasattr(L, "ora_adjoint_step"):
             L.ora_adjoint_step.argtypes = [P, _D, _D, _D, _D]
             L.ora_objective.argtypes = [P, ctypes.c_int, _D, _D, _D, _D]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's row loops."""
+    return int(lib().ora_threads())
 
 
 def _ptr(a: np.ndarray | None):

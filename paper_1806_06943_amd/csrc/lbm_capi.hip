@@ -1,0 +1,510 @@
+// C-ABI entry points (include/lbm.h): validation, workspace layout, context
+// bookkeeping and HIP-graph replay of the step loop.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: parity unchanged)
+constexpr uint64_t ALIGN = 256;
+
+thread_local std::string g_init_error;
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+struct InstLayout {
+    int32_t pitch;
+    int64_t plane;       // floats
+    uint64_t bytes;      // per-instance bytes (f0, f1, rho, fld)
+};
+
+InstLayout inst_layout(const lbm_params &p)
+{
+    InstLayout L;
+    L.pitch = (int32_t)align_up((uint64_t)p.nx, 64);
+    // pad each plane so that consecutive planes do not sit at the same offset
+    // modulo large powers of two
+    L.plane = (int64_t)align_up((uint64_t)p.ny * L.pitch, 64) + 64;
+    L.bytes = align_up((uint64_t)(18 + 18 + 2 + NFLD) * L.plane * sizeof(float), ALIGN);
+    return L;
+}
+
+struct Layout {
+    uint64_t off_insts, off_tiles, off_rows, off_row0s, off_rho0p, off_part, off_res, off_data;
+    std::vector<uint64_t> off_inst;
+    std::vector<InstLayout> inst;
+    int ntiles = 0, nrows = 0;
+    uint64_t total = 0;
+};
+
+Layout make_layout(const lbm_params *p, int n)
+{
+    Layout L;
+    for (int i = 0; i < n; ++i) {
+        L.ntiles += ((p[i].nx + TX - 1) / TX) * ((p[i].ny + TY - 1) / TY);
+        L.nrows += p[i].ny;
+    }
+    uint64_t o = 0;
+    L.off_insts = o; o = align_up(o + sizeof(KInst) * n, ALIGN);
+    L.off_tiles = o; o = align_up(o + sizeof(int4) * L.ntiles, ALIGN);
+    L.off_rows = o;  o = align_up(o + sizeof(int2) * L.nrows, ALIGN);
+    L.off_row0s = o; o = align_up(o + sizeof(int) * n, ALIGN);
+    L.off_rho0p = o; o = align_up(o + sizeof(double *) * n, ALIGN);
+    L.off_part = o;  o = align_up(o + sizeof(double) * NQR * (uint64_t)L.nrows, ALIGN);
+    L.off_res = o;   o = align_up(o + sizeof(double) * NRES * (uint64_t)n, ALIGN);
+    L.off_data = o;
+    for (int i = 0; i < n; ++i) {
+        L.inst.push_back(inst_layout(p[i]));
+        L.off_inst.push_back(o);
+        o += L.inst.back().bytes;
+    }
+    L.total = o;
+    return L;
+}
+
+bool finite_all(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+// returns an empty string when p is valid
+std::string check_params(const lbm_params &p)
+{
+    char buf[256];
+    if (p.nx < 1 || p.ny < 1) {
+        snprintf(buf, sizeof buf, "lattice size must be >= 1 (got %d x %d)", p.nx, p.ny);
+        return buf;
+    }
+    if ((int64_t)p.nx * p.ny > (int64_t)1 << 30) return "lattice larger than 2^30 nodes";
+    if (p.walls != 0 && p.walls != 1) return "walls must be 0 or 1";
+    if (p.reserved != 0) return "reserved field must be 0";
+    const double *d = &p.G_AB;
+    if (!finite_all(d, (int)((sizeof(lbm_params) - offsetof(lbm_params, G_AB)) / sizeof(double))))
+        return "parameters must be finite";
+    for (int k = 0; k < 2; ++k)
+        if (!(p.tau[k] > 0.5)) {
+            snprintf(buf, sizeof buf, "tau[%d] = %g must exceed 0.5", k, p.tau[k]);
+            return buf;
+        }
+    if (!(p.psi_rho0 > 0)) return "psi_rho0 must be positive";
+    return "";
+}
+
+KInst make_kinst(const lbm_params &p, const InstLayout &L, char *base)
+{
+    KInst K;
+    std::memset(&K, 0, sizeof K);
+    float *b = (float *)base;
+    K.f[0] = b;
+    K.f[1] = b + 18 * L.plane;
+    K.rho = b + 36 * L.plane;
+    K.fld = b + 38 * L.plane;
+    K.plane = L.plane;
+    K.nx = p.nx;
+    K.ny = p.ny;
+    K.pitch = L.pitch;
+    K.walls = p.walls;
+    // merged weights of Eq. 8 per |e|^2 class {1, 2, 4, 5, 8}
+    const double w[5] = {1.0 / 9.0, 1.0 / 36.0, 0.0, 0.0, 0.0};
+    const double pw[5] = {4.0 / 63.0, 4.0 / 135.0, 1.0 / 180.0, 2.0 / 945.0, 1.0 / 15120.0};
+    for (int k = 0; k < 2; ++k) {
+        for (int c = 0; c < 5; ++c) K.cw[k][c] = (float)(p.G1[k] * w[c] + p.G2[k] * pw[c]);
+        K.g[k][0] = (float)p.g[k][0];
+        K.g[k][1] = (float)p.g[k][1];
+        K.it[k] = (float)(1.0 / p.tau[k]);
+        K.cf[k] = (float)((1.0 - 0.5 / p.tau[k]) / 36.0);
+        K.rho_ref[k] = (float)p.rho_ref[k];
+        K.rho_wall[k] = (float)p.rho_wall[k];
+        K.psi_wall[k] = (float)(p.psi_rho0 * -std::expm1(-p.rho_wall[k] / p.psi_rho0));
+        K.gpb[k] = (float)(0.5 * (p.G1[k] + p.G2[k]));
+    }
+    K.gr1 = (float)(p.G_AB / 9.0);
+    K.gr2 = (float)(p.G_AB / 36.0);
+    K.gab = (float)p.G_AB;
+    K.rho0 = (float)p.psi_rho0;
+    K.inv_rho0 = (float)(1.0 / p.psi_rho0);
+    return K;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;        // private stream used only for graph capture
+    int n_inst = 0;
+    std::vector<lbm_params> params;
+    std::vector<KInst> hinst;
+    Layout layout;
+    Dev dev{};
+    char *ws = nullptr;
+    int par = 0;
+    int64_t steps = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+#define CTX_CHECK(ctx)                                   \
+    do {                                                 \
+        if (!(ctx)) return LBM_EINVAL;                   \
+    } while (0)
+
+static int fail(lbm_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_init_error = msg;
+    return code;
+}
+
+static int hip_fail(lbm_ctx *ctx, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, LBM_EHIP, m);
+}
+
+#define HIP_TRY(ctx, call)                                              \
+    do {                                                                \
+        hipError_t e__ = (call);                                        \
+        if (e__ != hipSuccess) return hip_fail((ctx), e__, #call);      \
+    } while (0)
+
+extern "C" {
+
+int lbm_workspace_bytes(const lbm_params *params, int32_t n_inst, uint64_t *bytes)
+{
+    if (!params || !bytes || n_inst < 1) return fail(nullptr, LBM_EINVAL, "null argument or n_inst < 1");
+    for (int i = 0; i < n_inst; ++i) {
+        std::string m = check_params(params[i]);
+        if (!m.empty()) return fail(nullptr, LBM_EINVAL, "instance " + std::to_string(i) + ": " + m);
+    }
+    *bytes = make_layout(params, n_inst).total;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const double *rhoA0,
+             const double *rhoB0, void *workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!out || !params || !rhoA0 || !rhoB0 || !workspace || n_inst < 1)
+        return fail(nullptr, LBM_EINVAL, "null argument or n_inst < 1");
+    *out = nullptr;
+    if ((uintptr_t)workspace % ALIGN)
+        return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    for (int i = 0; i < n_inst; ++i) {
+        std::string m = check_params(params[i]);
+        if (!m.empty()) return fail(nullptr, LBM_EINVAL, "instance " + std::to_string(i) + ": " + m);
+    }
+    Layout L = make_layout(params, n_inst);
+    if (workspace_bytes < L.total)
+        return fail(nullptr, LBM_EINVAL, "workspace too small: need " + std::to_string(L.total) +
+                                              " bytes, got " + std::to_string(workspace_bytes));
+
+    lbm_ctx *ctx = new lbm_ctx();
+    ctx->stream = (hipStream_t)stream;
+    ctx->n_inst = n_inst;
+    ctx->params.assign(params, params + n_inst);
+    ctx->layout = L;
+    ctx->ws = (char *)workspace;
+
+    // host tables
+    std::vector<int4> tiles;
+    std::vector<int2> rows;
+    std::vector<int> row0s;
+    std::vector<const double *> rho0p;
+    for (int i = 0; i < n_inst; ++i) {
+        const lbm_params &p = params[i];
+        ctx->hinst.push_back(make_kinst(p, L.inst[i], ctx->ws + L.off_inst[i]));
+        for (int y0 = 0; y0 < p.ny; y0 += TY)
+            for (int x0 = 0; x0 < p.nx; x0 += TX) tiles.push_back(make_int4(i, x0, y0, 0));
+        row0s.push_back((int)rows.size());
+        for (int y = 0; y < p.ny; ++y) rows.push_back(make_int2(i, y));
+        // FP64 initial densities are staged in the instance's field scratch
+        rho0p.push_back((const double *)ctx->hinst.back().fld);
+    }
+    Dev &d = ctx->dev;
+    d.insts = (KInst *)(ctx->ws + L.off_insts);
+    d.tiles = (int4 *)(ctx->ws + L.off_tiles);
+    d.rows = (int2 *)(ctx->ws + L.off_rows);
+    d.row0s = (int *)(ctx->ws + L.off_row0s);
+    d.part = (double *)(ctx->ws + L.off_part);
+    d.res = (double *)(ctx->ws + L.off_res);
+    d.ninst = n_inst;
+    d.ntiles = L.ntiles;
+    d.nrows = L.nrows;
+
+    hipStream_t st = ctx->stream;
+    auto bail = [&](hipError_t e, const char *what) {
+        std::string m = std::string(what) + ": " + hipGetErrorString(e);
+        delete ctx;
+        return fail(nullptr, LBM_EHIP, m);
+    };
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d.insts, ctx->hinst.data(), sizeof(KInst) * n_inst,
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy instance table");
+    if ((e = hipMemcpyAsync(d.tiles, tiles.data(), sizeof(int4) * tiles.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy tile table");
+    if ((e = hipMemcpyAsync(d.rows, rows.data(), sizeof(int2) * rows.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy row table");
+    if ((e = hipMemcpyAsync(d.row0s, row0s.data(), sizeof(int) * row0s.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy row offsets");
+    const double **drho0p = (const double **)(ctx->ws + L.off_rho0p);
+    if ((e = hipMemcpyAsync(drho0p, rho0p.data(), sizeof(double *) * n_inst,
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy density pointers");
+    uint64_t off = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const uint64_t N = (uint64_t)params[i].nx * params[i].ny;
+        double *dst = (double *)rho0p[i];
+        if ((e = hipMemcpyAsync(dst, rhoA0 + off, N * sizeof(double), hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return bail(e, "copy initial rho_A");
+        if ((e = hipMemcpyAsync(dst + N, rhoB0 + off, N * sizeof(double), hipMemcpyHostToDevice,
+                                st)) != hipSuccess)
+            return bail(e, "copy initial rho_B");
+        off += N;
+    }
+    if ((e = launch_init(d, drho0p, st)) != hipSuccess) return bail(e, "init kernel");
+    // the pageable host sources must stay valid until the copies complete
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "synchronise after init");
+    *out = ctx;
+    return LBM_OK;
+}
+
+static int step_eager(lbm_ctx *ctx, int64_t n, hipStream_t st)
+{
+    for (int64_t s = 0; s < n; ++s) {
+        hipError_t e = launch_step(ctx->dev, ctx->par, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+        ctx->par ^= 1;
+    }
+    return LBM_OK;
+}
+
+static int ensure_graph(lbm_ctx *ctx, int par)
+{
+    if (ctx->graph[par]) return LBM_OK;
+    if (!ctx->cap) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    int p = par;
+    for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s) {
+        le = launch_step(ctx->dev, p, ctx->cap);
+        p ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(ctx->cap, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(ctx, le, "step launch during capture");
+    }
+    if (ee != hipSuccess) return hip_fail(ctx, ee, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&ctx->graph[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+        ctx->graph[par] = nullptr;
+        return hip_fail(ctx, ie, "hipGraphInstantiate");
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *ctx, int64_t nsteps)
+{
+    CTX_CHECK(ctx);
+    if (nsteps < 0) return fail(ctx, LBM_EINVAL, "nsteps must be >= 0");
+    hipStream_t st = ctx->stream;
+    int64_t q = nsteps / GRAPH_STEPS, r = nsteps % GRAPH_STEPS;
+    if (q > 0) {
+        int rc = ensure_graph(ctx, ctx->par);
+        if (rc != LBM_OK) return rc;
+        for (int64_t i = 0; i < q; ++i) HIP_TRY(ctx, hipGraphLaunch(ctx->graph[ctx->par], st));
+    }
+    int rc = step_eager(ctx, r, st);
+    if (rc != LBM_OK) return rc;
+    ctx->steps += nsteps;
+    return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx *ctx) { return ctx ? ctx->steps : -1; }
+
+int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar)
+{
+    CTX_CHECK(ctx);
+    if (!out) return fail(ctx, LBM_EINVAL, "null output");
+    hipStream_t st = ctx->stream;
+    const double margin = 12.0;  // outer pressure shell starts 12 lattice units beyond R_eff
+    hipError_t e = launch_observables(ctx->dev, ctx->par, margin, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "observable kernels");
+    std::vector<double> res((size_t)NRES * ctx->n_inst);
+    HIP_TRY(ctx, hipMemcpyAsync(res.data(), ctx->dev.res, sizeof(double) * res.size(),
+                                hipMemcpyDeviceToHost, st));
+    std::vector<double> part;
+    if (ubar) {
+        part.resize((size_t)NQR * ctx->dev.nrows);
+        HIP_TRY(ctx, hipMemcpyAsync(part.data(), ctx->dev.part, sizeof(double) * part.size(),
+                                    hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    bool bad = false;
+    int row = 0;
+    for (int i = 0; i < ctx->n_inst; ++i) {
+        const double *R = res.data() + (size_t)NRES * i;
+        lbm_obs &o = out[i];
+        o.mass[0] = R[RES_MASSA];
+        o.mass[1] = R[RES_MASSB];
+        o.mom_raw[0] = R[RES_PX];
+        o.mom_raw[1] = R[RES_PY];
+        o.mom_bary[0] = R[RES_JX];
+        o.mom_bary[1] = R[RES_JY];
+        o.max_speed = R[RES_UMAX];
+        o.rho_a_max = R[RES_AMAX];
+        o.rho_a_min = R[RES_AMIN];
+        o.flow_rate = R[RES_Q];
+        o.R_eff = R[RES_R];
+        o.cx = R[RES_CX];
+        o.cy = R[RES_CY];
+        o.p_in = R[RES_PIN];
+        o.p_out = R[RES_POUT];
+        o.dp = R[RES_DP];
+        o.gamma = R[RES_GAMMA];
+        o.width = R[RES_W];
+        o.n_in = (int64_t)R[RES_NIN];
+        o.n_out = (int64_t)R[RES_NOUT];
+        o.finite = R[RES_BAD] == 0.0 && std::isfinite(R[RES_MASSA]) && std::isfinite(R[RES_MASSB]);
+        if (!o.finite) bad = true;
+        if (ubar) {
+            const lbm_params &p = ctx->params[i];
+            for (int y = 0; y < p.ny; ++y) ubar[row + y] = part[(size_t)(row + y) * NQR + 6] / p.nx;
+        }
+        row += ctx->params[i].ny;
+    }
+    if (bad) return fail(ctx, LBM_ENONFINITE, "non-finite density or velocity in the state");
+    return LBM_OK;
+}
+
+static int check_inst(lbm_ctx *ctx, int32_t inst)
+{
+    if (inst < 0 || inst >= ctx->n_inst)
+        return fail(ctx, LBM_EINVAL, "instance index out of range");
+    return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx *ctx, int32_t inst, float *rho_dev, float *u_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    hipError_t e = launch_fields(ctx->dev, ctx->par, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fields kernels");
+    e = launch_fields_out(ctx->dev, inst, rho_dev, u_dev, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "fields copy kernel");
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *ctx, int32_t inst, float *f_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!f_dev) return fail(ctx, LBM_EINVAL, "null output");
+    hipError_t e = launch_export(ctx->dev, inst, ctx->par, f_dev, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "export kernel");
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *ctx, int32_t inst, const float *f_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!f_dev) return fail(ctx, LBM_EINVAL, "null input");
+    hipError_t e = launch_import(ctx->dev, inst, ctx->par, f_dev, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "import kernel");
+    ctx->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_forces(lbm_ctx *ctx, int32_t inst, const float *rho_dev, float *F_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!rho_dev || !F_dev) return fail(ctx, LBM_EINVAL, "null argument");
+    hipError_t e = launch_forces(ctx->dev, inst, rho_dev, F_dev, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "force kernels");
+    return LBM_OK;
+}
+
+int lbm_copy_probe(lbm_ctx *ctx, void *dst_dev, const void *src_dev, uint64_t nbytes)
+{
+    CTX_CHECK(ctx);
+    if (!dst_dev || !src_dev) return fail(ctx, LBM_EINVAL, "null argument");
+    if (((uintptr_t)dst_dev | (uintptr_t)src_dev) % 16)
+        return fail(ctx, LBM_EINVAL, "copy buffers must be 16-byte aligned");
+    hipError_t e = launch_copy(dst_dev, src_dev, nbytes, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy kernel");
+    return LBM_OK;
+}
+
+int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, const char **names,
+                     int32_t *n_kernels)
+{
+    CTX_CHECK(ctx);
+    if (nrep < 1 || !ms || !n_kernels || max_k < 0) return fail(ctx, LBM_EINVAL, "bad arguments");
+    *n_kernels = N_STEP_KERNELS;
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    int rc = LBM_OK;
+    // the density pass first, so that the step kernel reads current densities
+    for (int j = 0; j < N_STEP_KERNELS && j < max_k && rc == LBM_OK; ++j) {
+        hipError_t e = launch_step_kernel(ctx->dev, j, ctx->par, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < nrep && e == hipSuccess; ++r) e = launch_step_kernel(ctx->dev, j, ctx->par, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(ctx, e, "profile launches");
+            break;
+        }
+        ms[j] = (double)t / nrep;
+        if (names) names[j] = step_kernel_name(j);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int lbm_destroy(lbm_ctx *ctx)
+{
+    if (!ctx) return LBM_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->graph[i]) (void)hipGraphExecDestroy(ctx->graph[i]);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    delete ctx;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// Device-side pieces of the two-range pseudopotential LBM step for gfx950
+// (arXiv:1806.06943, Sec. II): per-instance launch parameters, the D2Q9 pull
+// gather, the two-belt force from an LDS density tile and the FP32 collision.
+//
+// Numerical formulation (FP32 throughout the step):
+//   * populations are stored after collision as deviations f* - w_i rho_ref;
+//     the next step pulls f_i(x) = f*_i(x - e_i) (bounce-back f*_opp(i)(x)
+//     when x - e_i lies beyond a wall);
+//   * the density deviation sum uses error-free TwoSum accumulation, so the
+//     rest-state part of the collision sees the stored mass exactly;
+//   * weights are w_i = c_i / 36 with integer c_i = 16, 4, 1; quantities per
+//     unit weight are formed by a correctly rounded division by 36, so the
+//     rounding of the weights cannot create or destroy mass systematically;
+//   * the collision relaxes only the small part f_i - c_i a (a = drho / 36)
+//     and adds the rest part back once;
+//   * the force stencils of Eqs. 8 and 9 are evaluated as antisymmetric
+//     differences psi(x+e) - psi(x-e) with the two couplings of Eq. 8 merged
+//     per |e|^2 class, which keeps the exact pairwise momentum balance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int TX = 64;   // tile width  (one wavefront of 64 lanes per row)
+constexpr int TY = 4;    // tile height (4 wavefronts per block)
+constexpr int NTHREADS = TX * TY;
+constexpr int HALO = 2;  // radius of the D2Q25 stencil
+
+// number of FP32 planes in the per-instance field scratch
+constexpr int NFLD = 9;
+enum FieldPlane { FLD_RHOA = 0, FLD_RHOB, FLD_UX, FLD_UY, FLD_PB, FLD_MX, FLD_MY, FLD_JX, FLD_JY };
+
+// Launch parameters of one instance (device copy lives in the workspace).
+struct KInst {
+    float *f[2];           // population buffers [k][i] planes of ny rows x pitch floats
+    float *rho;            // density planes [k], written by the density pass
+    float *fld;            // field scratch planes [NFLD]
+    int64_t plane;         // floats between consecutive planes of f, rho and fld
+    int32_t nx, ny, pitch, walls;
+    float cw[2][5];        // merged Eq. 8 weights G1 w + G2 p per |e|^2 in {1, 2, 4, 5, 8}
+    float gr1, gr2;        // Eq. 9 weights G_AB w(1), G_AB w(2)
+    float g[2][2];         // body acceleration per component
+    float it[2];           // 1 / tau_k
+    float cf[2];           // (1 - 1/(2 tau_k)) / 36
+    float rho_ref[2];
+    float rho_wall[2], psi_wall[2];
+    float rho0, inv_rho0;  // pseudopotential scale
+    float gpb[2];          // (G1 + G2) / 2 per component, for the bulk pressure of Eq. 11
+    float gab;             // G_AB
+    int32_t pad_;
+};
+
+__device__ __forceinline__ int wrapi(int a, int n)
+{
+    if (a >= 0 && a < n) return a;
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// psi = rho0 (1 - exp(-rho/rho0)), through expm1f for accuracy at small rho
+__device__ __forceinline__ float psi_of(const KInst &P, float r)
+{
+    return -P.rho0 * expm1f(-r * P.inv_rho0);
+}
+
+// Pre-collision populations of node (x, y): pull from post-collision storage.
+// D2Q9 order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
+// 7:(-1,-1) 8:(1,-1).
+__device__ __forceinline__ void gather(const KInst &P, const float *__restrict__ fc, int x,
+                                       int y, float f[2][9])
+{
+    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
+    const int64_t pl = P.plane;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    bool lo_wall = false, hi_wall = false;
+    int ym, yp;
+    if (P.walls) {
+        lo_wall = (y == 0);
+        hi_wall = (y == ny - 1);
+        ym = y - 1;
+        yp = y + 1;
+    } else {
+        ym = (y == 0) ? ny - 1 : y - 1;
+        yp = (y == ny - 1) ? 0 : y + 1;
+    }
+    const int64_t r0 = (int64_t)y * pitch;
+    const int64_t rm = (int64_t)ym * pitch;
+    const int64_t rp = (int64_t)yp * pitch;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float *b = fc + (int64_t)k * 9 * pl;
+        f[k][0] = b[0 * pl + r0 + x];
+        f[k][1] = b[1 * pl + r0 + xm];
+        f[k][3] = b[3 * pl + r0 + xp];
+        // directions with e_y = +1 come from row y-1
+        if (lo_wall) {
+            f[k][2] = b[4 * pl + r0 + x];
+            f[k][5] = b[7 * pl + r0 + x];
+            f[k][6] = b[8 * pl + r0 + x];
+        } else {
+            f[k][2] = b[2 * pl + rm + x];
+            f[k][5] = b[5 * pl + rm + xm];
+            f[k][6] = b[6 * pl + rm + xp];
+        }
+        // directions with e_y = -1 come from row y+1
+        if (hi_wall) {
+            f[k][4] = b[2 * pl + r0 + x];
+            f[k][7] = b[5 * pl + r0 + x];
+            f[k][8] = b[6 * pl + r0 + x];
+        } else {
+            f[k][4] = b[4 * pl + rp + x];
+            f[k][7] = b[7 * pl + rp + xp];
+            f[k][8] = b[8 * pl + rp + xm];
+        }
+    }
+}
+
+// Error-free sum of the nine deviations: drho = hi + lo exactly up to the
+// final representation (Knuth TwoSum per term).
+__device__ __forceinline__ void sum9(const float f[9], float &hi, float &lo)
+{
+    float s = f[0], c = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const float t = s + f[i];
+        const float bp = t - s;
+        c += (s - (t - bp)) + (f[i] - bp);
+        s = t;
+    }
+    hi = s;
+    lo = c;
+}
+
+// LDS density tile: rho and psi of both components on the tile plus a halo
+// of 2, laid out [k][row][col] with (TX + 4) columns.
+struct Tile {
+    float rho[2][TY + 2 * HALO][TX + 2 * HALO];
+    float psi[2][TY + 2 * HALO][TX + 2 * HALO];
+};
+
+// Fill the LDS tile for the tile whose first node is (x0, y0).  Periodic wrap
+// in x (and in y without walls); rows beyond a wall hold the wall densities.
+__device__ __forceinline__ void stage_tile(const KInst &P, int x0, int y0, Tile &T)
+{
+    constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO;
+    const int64_t pl = P.plane;
+    for (int t = threadIdx.x; t < W * H; t += NTHREADS) {
+        const int lx = t % W, ly = t / W;
+        const int gx = wrapi(x0 + lx - HALO, P.nx);
+        int gy = y0 + ly - HALO;
+        float rA, rB, pA, pB;
+        if (P.walls && (gy < 0 || gy >= P.ny)) {
+            rA = P.rho_wall[0];
+            rB = P.rho_wall[1];
+            pA = P.psi_wall[0];
+            pB = P.psi_wall[1];
+        } else {
+            gy = wrapi(gy, P.ny);
+            const int64_t o = (int64_t)gy * P.pitch + gx;
+            rA = P.rho[o];
+            rB = P.rho[pl + o];
+            pA = psi_of(P, rA);
+            pB = psi_of(P, rB);
+        }
+        T.rho[0][ly][lx] = rA;
+        T.rho[1][ly][lx] = rB;
+        T.psi[0][ly][lx] = pA;
+        T.psi[1][ly][lx] = pB;
+    }
+}
+
+// Total force on both components at LDS position (cx, cy) of the tile
+// (cx, cy include the halo offset).  F^c (Eq. 8) with merged weights,
+// F^r (Eq. 9), F^b = rho g.
+__device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx, int cy,
+                                           float F[2][2])
+{
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float(*ps)[TX + 2 * HALO] = T.psi[k];
+        const float(*rb)[TX + 2 * HALO] = T.rho[1 - k];
+#define PSI(dx, dy) ps[cy + (dy)][cx + (dx)]
+#define RHB(dx, dy) rb[cy + (dy)][cx + (dx)]
+        // antisymmetric pair differences d(e) = psi(x+e) - psi(x-e)
+        const float d10 = PSI(1, 0) - PSI(-1, 0);
+        const float d20 = PSI(2, 0) - PSI(-2, 0);
+        const float d01 = PSI(0, 1) - PSI(0, -1);
+        const float d02 = PSI(0, 2) - PSI(0, -2);
+        const float d11 = PSI(1, 1) - PSI(-1, -1);
+        const float dm11 = PSI(-1, 1) - PSI(1, -1);
+        const float d21 = PSI(2, 1) - PSI(-2, -1);
+        const float dm21 = PSI(-2, 1) - PSI(2, -1);
+        const float d12 = PSI(1, 2) - PSI(-1, -2);
+        const float dm12 = PSI(-1, 2) - PSI(1, -2);
+        const float d22 = PSI(2, 2) - PSI(-2, -2);
+        const float dm22 = PSI(-2, 2) - PSI(2, -2);
+        const float c1 = P.cw[k][0], c2 = P.cw[k][1], c4 = P.cw[k][2], c5 = P.cw[k][3],
+                    c8 = P.cw[k][4];
+        const float sx = c1 * d10 + 2.0f * c4 * d20 + c2 * (d11 - dm11) +
+                         c5 * (2.0f * (d21 - dm21) + (d12 - dm12)) + 2.0f * c8 * (d22 - dm22);
+        const float sy = c1 * d01 + 2.0f * c4 * d02 + c2 * (d11 + dm11) +
+                         c5 * ((d21 + dm21) + 2.0f * (d12 + dm12)) + 2.0f * c8 * (d22 + dm22);
+        // inter-species repulsion acts through the other component's density
+        const float r10 = RHB(1, 0) - RHB(-1, 0);
+        const float r01 = RHB(0, 1) - RHB(0, -1);
+        const float r11 = RHB(1, 1) - RHB(-1, -1);
+        const float rm11 = RHB(-1, 1) - RHB(1, -1);
+        const float rx = P.gr1 * r10 + P.gr2 * (r11 - rm11);
+        const float ry = P.gr1 * r01 + P.gr2 * (r11 + rm11);
+#undef PSI
+#undef RHB
+        const float psi0 = T.psi[k][cy][cx];
+        const float rho0 = T.rho[k][cy][cx];
+        F[k][0] = -psi0 * sx - rho0 * rx + rho0 * P.g[k][0];
+        F[k][1] = -psi0 * sy - rho0 * ry + rho0 * P.g[k][1];
+    }
+}
+
+// Momentum sum_i f_i e_i of one component as antisymmetric differences.
+__device__ __forceinline__ void mom9(const float f[9], float &mx, float &my)
+{
+    mx = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
+    my = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+}
+
+// Common velocity u^eq of Eq. 3 from the component momenta j_k (with F/2).
+__device__ __forceinline__ void common_velocity(const KInst &P, const float rho[2],
+                                                const float jx[2], const float jy[2], float &ux,
+                                                float &uy)
+{
+    const float den = rho[0] * P.it[0] + rho[1] * P.it[1];
+    ux = (jx[0] * P.it[0] + jx[1] * P.it[1]) / den;
+    uy = (jy[0] * P.it[0] + jy[1] * P.it[1]) / den;
+}
+
+// BGK + Guo collision of one component (Eqs. 1, 2 with the 1/2 on the
+// quadratic term, 5), in deviation form.  f: pre-collision deviations,
+// (dh, dl): their exact sum, rho: density, F: force, (ux, uy): u^eq.
+__device__ __forceinline__ void collide(const KInst &P, int k, const float f[9], float dh,
+                                        float dl, float rho, float Fx, float Fy, float ux,
+                                        float uy, float out[9])
+{
+    constexpr float EXf[9] = {0.f, 1.f, 0.f, -1.f, 0.f, 1.f, -1.f, -1.f, 1.f};
+    constexpr float EYf[9] = {0.f, 0.f, 1.f, 0.f, -1.f, 1.f, 1.f, -1.f, -1.f};
+    constexpr float CI[9] = {16.f, 4.f, 4.f, 4.f, 4.f, 1.f, 1.f, 1.f, 1.f};
+    const float a = (dh + dl) / 36.0f;   // rest-state deviation per unit weight
+    const float r36 = rho / 36.0f;
+    const float it = P.it[k];
+    const float cf = P.cf[k];
+    const float uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float ex = EXf[i], ey = EYf[i];
+        const float eu = ex * ux + ey * uy;
+        const float q = eu * (3.0f + 4.5f * eu) - 1.5f * uu;
+        const float feqs = CI[i] * (r36 * q);
+        const float eF = ex * Fx + ey * Fy;
+        const float cterm = 3.0f * ((ex - ux) * Fx + (ey - uy) * Fy) + 9.0f * eu * eF;
+        const float C = CI[i] * (cf * cterm);
+        const float rest = CI[i] * a;
+        const float gi = f[i] - rest;
+        const float small = gi + (feqs - gi) * it + C;
+        out[i] = rest + small;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,43 @@
+// Host/device shared declarations of the HIP library (not part of the C-ABI).
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// per-row partial quantities and per-instance results of the FP64 reductions
+constexpr int NQR = 12;
+constexpr int NRES = 24;
+enum ResSlot {
+    RES_MASSA = 0, RES_MASSB, RES_PX, RES_PY, RES_JX, RES_JY, RES_Q, RES_UMAX, RES_AMAX,
+    RES_AMIN, RES_BAD, RES_AREA, RES_R, RES_CX, RES_CY, RES_PIN, RES_POUT, RES_NIN, RES_NOUT,
+    RES_DP, RES_GAMMA, RES_W
+};
+
+// device-side tables of a context (all inside the caller's workspace)
+struct Dev {
+    KInst *insts;   // [ninst]
+    int4 *tiles;    // [ntiles] {inst, x0, y0, 0}
+    int2 *rows;     // [nrows]  {inst, y}
+    int *row0s;     // [ninst]  first row index of each instance in rows
+    double *part;   // [nrows][NQR]
+    double *res;    // [ninst][NRES]
+    int ninst, ntiles, nrows;
+};
+
+hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
+hipError_t launch_step(const Dev &d, int par, hipStream_t st);
+hipError_t launch_fields(const Dev &d, int par, hipStream_t st);
+hipError_t launch_fields_out(const Dev &d, int inst, float *rho, float *u, hipStream_t st);
+hipError_t launch_export(const Dev &d, int inst, int par, float *f, hipStream_t st);
+hipError_t launch_import(const Dev &d, int inst, int par, const float *f, hipStream_t st);
+hipError_t launch_forces(const Dev &d, int inst, const float *rho, float *F, hipStream_t st);
+hipError_t launch_observables(const Dev &d, int par, double margin, hipStream_t st);
+hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t st);
+
+// kernels of one step, for timing: number, names, and a launcher of kernel j
+constexpr int N_STEP_KERNELS = 2;
+const char *step_kernel_name(int j);
+hipError_t launch_step_kernel(const Dev &d, int j, int par, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,67 @@
+"""Host-side checks of the HIP library: it loads, exports every entry point that
+include/lbm.h declares, and validates parameters (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1806_06943_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.lib()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _ok_params(**kw):
+    base = dict(nx=16, ny=8, G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.6))
+    base.update(kw)
+    return lbm.make_params(**base)
+
+
+def test_workspace_bytes_and_validation():
+    b1 = lbm.lbm_workspace_bytes([_ok_params()])
+    b2 = lbm.lbm_workspace_bytes([_ok_params(), _ok_params(nx=64, ny=64)])
+    assert b1 > 16 * 8 * 47 * 4 and b2 > b1
+    for bad in [dict(tau=(0.5, 1.0)), dict(tau=(1.0, 0.2)), dict(nx=0), dict(ny=-3),
+                dict(walls=2), dict(G_AB=float("nan"))]:
+        with pytest.raises(lbm.LBMError) as ei:
+            lbm.lbm_workspace_bytes([_ok_params(**bad)])
+        assert ei.value.code == lbm.LBM_EINVAL
+    p = _ok_params()
+    p.reserved = 7
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_workspace_bytes([p])
+
+
+def test_init_rejects_bad_arguments_without_touching_the_gpu():
+    L = lbm.lib()
+    p = (lbm.lbm_params * 1)(_ok_params())
+    ctx = ctypes.c_void_p()
+    rho = (ctypes.c_double * (16 * 8))()
+    # null workspace
+    rc = L.lbm_init(ctypes.byref(ctx), p, 1, rho, rho, None, 0, None)
+    assert rc == lbm.LBM_EINVAL
+    # misaligned workspace pointer (never dereferenced: rejected first)
+    rc = L.lbm_init(ctypes.byref(ctx), p, 1, rho, rho, ctypes.c_void_p(0x1001), 1 << 30, None)
+    assert rc == lbm.LBM_EINVAL
+    assert b"aligned" in L.lbm_last_error(None)
+    # too small
+    rc = L.lbm_init(ctypes.byref(ctx), p, 1, rho, rho, ctypes.c_void_p(0x10000), 16, None)
+    assert rc == lbm.LBM_EINVAL
+    assert b"too small" in L.lbm_last_error(None)
+    # null context handles
+    assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
+    assert L.lbm_destroy(None) == lbm.LBM_EINVAL
