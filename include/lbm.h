@@ -152,6 +152,13 @@ int lbm_copy_probe(lbm_ctx *ctx, void *dst_dev, const void *src_dev, uint64_t nb
 int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, const char **names,
                      int32_t *n_kernels);
 
+/* Strip height of the fused step (lattice rows one wavefront advances per
+ * step, default 16, at least 4).  Any value gives the same results bit for
+ * bit; it trades halo recomputation against parallelism.  Synchronises the
+ * stream and discards captured graphs. */
+int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows);
+int32_t lbm_get_tiling(const lbm_ctx *ctx);
+
 /* Release host resources of the context (graphs, metadata).  Synchronises
  * the stream; never frees caller memory. */
 int lbm_destroy(lbm_ctx *ctx);

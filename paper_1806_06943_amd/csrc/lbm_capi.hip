@@ -15,6 +15,8 @@ namespace {
 
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: parity unchanged)
 constexpr uint64_t ALIGN = 256;
+constexpr int MIN_CHUNK = 4;     // smallest strip height the workspace is sized for
+constexpr int DEFAULT_CHUNK = 16;
 
 thread_local std::string g_init_error;
 
@@ -33,17 +35,57 @@ InstLayout inst_layout(const lbm_params &p)
     // pad each plane so that consecutive planes do not sit at the same offset
     // modulo large powers of two
     L.plane = (int64_t)align_up((uint64_t)p.ny * L.pitch, 64) + 64;
-    L.bytes = align_up((uint64_t)(18 + 18 + 2 + NFLD) * L.plane * sizeof(float), ALIGN);
+    L.bytes = align_up((uint64_t)(18 + 18 + 2 + 2 + NFLD) * L.plane * sizeof(float), ALIGN);
     return L;
 }
 
 struct Layout {
-    uint64_t off_insts, off_tiles, off_rows, off_row0s, off_rho0p, off_part, off_res, off_data;
+    uint64_t off_insts, off_tiles, off_strips, off_rows, off_row0s, off_rho0p, off_part, off_res,
+        off_data;
     std::vector<uint64_t> off_inst;
     std::vector<InstLayout> inst;
-    int ntiles = 0, nrows = 0;
+    int ntiles = 0, nrows = 0, max_strips = 0;
     uint64_t total = 0;
 };
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Strips of the fused step for strip height H: per instance, columns are
+// split into ceil(nx / 62) strips of balanced width and rows into
+// ceil(ny / H) chunks of balanced height.  The table is then ordered so that
+// consecutive workgroup indices, which the hardware deals round-robin to the
+// eight XCDs, give each XCD a contiguous run of neighbouring strips (shared
+// halo columns and rows stay in that XCD's L2).
+std::vector<int4> make_strips(const lbm_params *p, int n, int H)
+{
+    std::vector<int4> tab;
+    for (int i = 0; i < n; ++i) {
+        const int ns = ceil_div(p[i].nx, SWO), nc = ceil_div(p[i].ny, H);
+        for (int c = 0; c < nc; ++c) {
+            const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
+            for (int sx = 0; sx < ns; ++sx) {
+                const int x0 = (int)((int64_t)p[i].nx * sx / ns);
+                const int x1 = (int)((int64_t)p[i].nx * (sx + 1) / ns);
+                tab.push_back(make_int4(i, x0, y0, (x1 - x0) | ((y1 - y0) << 16)));
+            }
+        }
+    }
+    constexpr int NXCD = 8;
+    const int T = (int)tab.size(), q = ceil_div(T, NXCD);
+    std::vector<int4> out;
+    out.reserve(T);
+    for (int m = 0; m < q; ++m)
+        for (int j = 0; j < NXCD; ++j)
+            if (j * q + m < T && m < q) out.push_back(tab[j * q + m]);
+    return out;
+}
+
+int max_strips(const lbm_params *p, int n)
+{
+    int t = 0;
+    for (int i = 0; i < n; ++i) t += ceil_div(p[i].nx, SWO) * ceil_div(p[i].ny, MIN_CHUNK);
+    return t;
+}
 
 Layout make_layout(const lbm_params *p, int n)
 {
@@ -52,9 +94,11 @@ Layout make_layout(const lbm_params *p, int n)
         L.ntiles += ((p[i].nx + TX - 1) / TX) * ((p[i].ny + TY - 1) / TY);
         L.nrows += p[i].ny;
     }
+    L.max_strips = max_strips(p, n);
     uint64_t o = 0;
     L.off_insts = o; o = align_up(o + sizeof(KInst) * n, ALIGN);
     L.off_tiles = o; o = align_up(o + sizeof(int4) * L.ntiles, ALIGN);
+    L.off_strips = o; o = align_up(o + sizeof(int4) * L.max_strips, ALIGN);
     L.off_rows = o;  o = align_up(o + sizeof(int2) * L.nrows, ALIGN);
     L.off_row0s = o; o = align_up(o + sizeof(int) * n, ALIGN);
     L.off_rho0p = o; o = align_up(o + sizeof(double *) * n, ALIGN);
@@ -107,8 +151,9 @@ KInst make_kinst(const lbm_params &p, const InstLayout &L, char *base)
     float *b = (float *)base;
     K.f[0] = b;
     K.f[1] = b + 18 * L.plane;
-    K.rho = b + 36 * L.plane;
-    K.fld = b + 38 * L.plane;
+    K.rho[0] = b + 36 * L.plane;
+    K.rho[1] = b + 38 * L.plane;
+    K.fld = b + 40 * L.plane;
     K.plane = L.plane;
     K.nx = p.nx;
     K.ny = p.ny;
@@ -150,6 +195,7 @@ struct lbm_ctx {
     int par = 0;
     int64_t steps = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int chunk = DEFAULT_CHUNK;
     std::string err;
 };
 
@@ -238,9 +284,12 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.row0s = (int *)(ctx->ws + L.off_row0s);
     d.part = (double *)(ctx->ws + L.off_part);
     d.res = (double *)(ctx->ws + L.off_res);
+    d.strips = (int4 *)(ctx->ws + L.off_strips);
     d.ninst = n_inst;
     d.ntiles = L.ntiles;
     d.nrows = L.nrows;
+    std::vector<int4> strips = make_strips(params, n_inst, ctx->chunk);
+    d.nstrips = (int)strips.size();
 
     hipStream_t st = ctx->stream;
     auto bail = [&](hipError_t e, const char *what) {
@@ -255,6 +304,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     if ((e = hipMemcpyAsync(d.tiles, tiles.data(), sizeof(int4) * tiles.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e, "copy tile table");
+    if ((e = hipMemcpyAsync(d.strips, strips.data(), sizeof(int4) * strips.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy strip table");
     if ((e = hipMemcpyAsync(d.rows, rows.data(), sizeof(int2) * rows.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e, "copy row table");
@@ -443,7 +495,7 @@ int lbm_forces(lbm_ctx *ctx, int32_t inst, const float *rho_dev, float *F_dev)
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
     if (!rho_dev || !F_dev) return fail(ctx, LBM_EINVAL, "null argument");
-    hipError_t e = launch_forces(ctx->dev, inst, rho_dev, F_dev, ctx->stream);
+    hipError_t e = launch_forces(ctx->dev, inst, ctx->par, rho_dev, F_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "force kernels");
     return LBM_OK;
 }
@@ -490,6 +542,29 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     (void)hipEventDestroy(e1);
     return rc;
 }
+
+int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
+{
+    CTX_CHECK(ctx);
+    if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
+        return fail(ctx, LBM_EINVAL, "chunk_rows must be in [4, 65535]");
+    std::vector<int4> strips = make_strips(ctx->params.data(), ctx->n_inst, chunk_rows);
+    if ((int)strips.size() > ctx->layout.max_strips) return fail(ctx, LBM_EINVAL, "strip table overflow");
+    // the table is read by kernels already queued: order the copy after them
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, strips.data(), sizeof(int4) * strips.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->dev.nstrips = (int)strips.size();
+    ctx->chunk = chunk_rows;
+    for (int i = 0; i < 2; ++i)
+        if (ctx->graph[i]) {
+            (void)hipGraphExecDestroy(ctx->graph[i]);
+            ctx->graph[i] = nullptr;
+        }
+    return LBM_OK;
+}
+
+int32_t lbm_get_tiling(const lbm_ctx *ctx) { return ctx ? ctx->chunk : -1; }
 
 int lbm_destroy(lbm_ctx *ctx)
 {

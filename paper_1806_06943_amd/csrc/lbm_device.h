@@ -2,10 +2,11 @@
 // (arXiv:1806.06943, Sec. II): per-instance launch parameters, the D2Q9 pull
 // gather, the two-belt force from an LDS density tile and the FP32 collision.
 //
+// Storage: the state at time t is the post-streaming, pre-collision
+// populations f(t) as FP32 deviations f - w_i rho_ref, plus the densities
+// rho(t) (double-buffered with rho(t+1)).
+//
 // Numerical formulation (FP32 throughout the step):
-//   * populations are stored after collision as deviations f* - w_i rho_ref;
-//     the next step pulls f_i(x) = f*_i(x - e_i) (bounce-back f*_opp(i)(x)
-//     when x - e_i lies beyond a wall);
 //   * the density deviation sum uses error-free TwoSum accumulation, so the
 //     rest-state part of the collision sees the stored mass exactly;
 //   * weights are w_i = c_i / 36 with integer c_i = 16, 4, 1; quantities per
@@ -23,10 +24,16 @@
 
 namespace lbm {
 
-constexpr int TX = 64;   // tile width  (one wavefront of 64 lanes per row)
-constexpr int TY = 4;    // tile height (4 wavefronts per block)
+constexpr int TX = 64;   // auxiliary 2-D tiles: width (one wavefront of 64 lanes per row)
+constexpr int TY = 4;    // auxiliary 2-D tiles: height (4 wavefronts per block)
 constexpr int NTHREADS = TX * TY;
 constexpr int HALO = 2;  // radius of the D2Q25 stencil
+
+// fused step: one wavefront per strip; lane l collides column X0 - 1 + l
+constexpr int SW = 64;           // lanes = collided columns of a strip
+constexpr int SWO = SW - 2;      // output columns of a full strip
+constexpr int RW = SW + 2 * HALO;  // density-ring columns (collided columns + stencil halo)
+constexpr int RR = 2 * HALO + 1;   // density-ring rows
 
 // number of FP32 planes in the per-instance field scratch
 constexpr int NFLD = 9;
@@ -35,7 +42,7 @@ enum FieldPlane { FLD_RHOA = 0, FLD_RHOB, FLD_UX, FLD_UY, FLD_PB, FLD_MX, FLD_MY
 // Launch parameters of one instance (device copy lives in the workspace).
 struct KInst {
     float *f[2];           // population buffers [k][i] planes of ny rows x pitch floats
-    float *rho;            // density planes [k], written by the density pass
+    float *rho[2];         // density buffers [k] planes, paired with f[]
     float *fld;            // field scratch planes [NFLD]
     int64_t plane;         // floats between consecutive planes of f, rho and fld
     int32_t nx, ny, pitch, walls;
@@ -65,57 +72,16 @@ __device__ __forceinline__ float psi_of(const KInst &P, float r)
     return -P.rho0 * expm1f(-r * P.inv_rho0);
 }
 
-// Pre-collision populations of node (x, y): pull from post-collision storage.
-// D2Q9 order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
-// 7:(-1,-1) 8:(1,-1).
-__device__ __forceinline__ void gather(const KInst &P, const float *__restrict__ fc, int x,
-                                       int y, float f[2][9])
+// Populations of node (x, y) from buffer fb (D2Q9 order 0:(0,0) 1:(1,0)
+// 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)).
+__device__ __forceinline__ void load_node(const KInst &P, const float *__restrict__ fb, int x,
+                                          int y, float f[2][9])
 {
-    const int nx = P.nx, ny = P.ny, pitch = P.pitch;
-    const int64_t pl = P.plane;
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
-    bool lo_wall = false, hi_wall = false;
-    int ym, yp;
-    if (P.walls) {
-        lo_wall = (y == 0);
-        hi_wall = (y == ny - 1);
-        ym = y - 1;
-        yp = y + 1;
-    } else {
-        ym = (y == 0) ? ny - 1 : y - 1;
-        yp = (y == ny - 1) ? 0 : y + 1;
-    }
-    const int64_t r0 = (int64_t)y * pitch;
-    const int64_t rm = (int64_t)ym * pitch;
-    const int64_t rp = (int64_t)yp * pitch;
+    const int64_t o = (int64_t)y * P.pitch + x;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float *b = fc + (int64_t)k * 9 * pl;
-        f[k][0] = b[0 * pl + r0 + x];
-        f[k][1] = b[1 * pl + r0 + xm];
-        f[k][3] = b[3 * pl + r0 + xp];
-        // directions with e_y = +1 come from row y-1
-        if (lo_wall) {
-            f[k][2] = b[4 * pl + r0 + x];
-            f[k][5] = b[7 * pl + r0 + x];
-            f[k][6] = b[8 * pl + r0 + x];
-        } else {
-            f[k][2] = b[2 * pl + rm + x];
-            f[k][5] = b[5 * pl + rm + xm];
-            f[k][6] = b[6 * pl + rm + xp];
-        }
-        // directions with e_y = -1 come from row y+1
-        if (hi_wall) {
-            f[k][4] = b[2 * pl + r0 + x];
-            f[k][7] = b[5 * pl + r0 + x];
-            f[k][8] = b[6 * pl + r0 + x];
-        } else {
-            f[k][4] = b[4 * pl + rp + x];
-            f[k][7] = b[7 * pl + rp + xp];
-            f[k][8] = b[8 * pl + rp + xm];
-        }
-    }
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[k][i] = fb[(int64_t)(k * 9 + i) * P.plane + o];
 }
 
 // Error-free sum of the nine deviations: drho = hi + lo exactly up to the
@@ -143,7 +109,8 @@ struct Tile {
 
 // Fill the LDS tile for the tile whose first node is (x0, y0).  Periodic wrap
 // in x (and in y without walls); rows beyond a wall hold the wall densities.
-__device__ __forceinline__ void stage_tile(const KInst &P, int x0, int y0, Tile &T)
+__device__ __forceinline__ void stage_tile(const KInst &P, const float *__restrict__ rb, int x0,
+                                           int y0, Tile &T)
 {
     constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO;
     const int64_t pl = P.plane;
@@ -160,8 +127,8 @@ __device__ __forceinline__ void stage_tile(const KInst &P, int x0, int y0, Tile 
         } else {
             gy = wrapi(gy, P.ny);
             const int64_t o = (int64_t)gy * P.pitch + gx;
-            rA = P.rho[o];
-            rB = P.rho[pl + o];
+            rA = rb[o];
+            rB = rb[pl + o];
             pA = psi_of(P, rA);
             pB = psi_of(P, rB);
         }
@@ -172,18 +139,17 @@ __device__ __forceinline__ void stage_tile(const KInst &P, int x0, int y0, Tile 
     }
 }
 
-// Total force on both components at LDS position (cx, cy) of the tile
-// (cx, cy include the halo offset).  F^c (Eq. 8) with merged weights,
-// F^r (Eq. 9), F^b = rho g.
-__device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx, int cy,
-                                           float F[2][2])
+// Total force on both components from a density/pseudopotential accessor:
+// acc.psi(k, dx, dy) and acc.rho(k, dx, dy) give the values at the node
+// displaced by (dx, dy).  F^c (Eq. 8) with merged weights, F^r (Eq. 9),
+// F^b = rho g.
+template <class Acc>
+__device__ __forceinline__ void stencil_force(const KInst &P, const Acc &acc, float F[2][2])
 {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        const float(*ps)[TX + 2 * HALO] = T.psi[k];
-        const float(*rb)[TX + 2 * HALO] = T.rho[1 - k];
-#define PSI(dx, dy) ps[cy + (dy)][cx + (dx)]
-#define RHB(dx, dy) rb[cy + (dy)][cx + (dx)]
+#define PSI(dx, dy) acc.psi(k, dx, dy)
+#define RHB(dx, dy) acc.rho(1 - k, dx, dy)
         // antisymmetric pair differences d(e) = psi(x+e) - psi(x-e)
         const float d10 = PSI(1, 0) - PSI(-1, 0);
         const float d20 = PSI(2, 0) - PSI(-2, 0);
@@ -212,12 +178,43 @@ __device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx
         const float ry = P.gr1 * r01 + P.gr2 * (r11 + rm11);
 #undef PSI
 #undef RHB
-        const float psi0 = T.psi[k][cy][cx];
-        const float rho0 = T.rho[k][cy][cx];
+        const float psi0 = acc.psi(k, 0, 0);
+        const float rho0 = acc.rho(k, 0, 0);
         F[k][0] = -psi0 * sx - rho0 * rx + rho0 * P.g[k][0];
         F[k][1] = -psi0 * sy - rho0 * ry + rho0 * P.g[k][1];
     }
 }
+
+// accessor into a 2-D LDS tile centred at (cx, cy)
+struct TileAcc {
+    const Tile &T;
+    int cx, cy;
+    __device__ float psi(int k, int dx, int dy) const { return T.psi[k][cy + dy][cx + dx]; }
+    __device__ float rho(int k, int dx, int dy) const { return T.rho[k][cy + dy][cx + dx]; }
+};
+
+__device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx, int cy,
+                                           float F[2][2])
+{
+    stencil_force(P, TileAcc{T, cx, cy}, F);
+}
+
+// Density ring of the fused step: RR rows (a rolling window over lattice
+// rows) of RW columns, column j holding lattice column X0 - 1 - HALO + j.
+struct Ring {
+    float rho[2][RR][RW];
+    float psi[2][RR][RW];
+};
+
+// accessor into the ring: slot[dy + 2] is the ring row of lattice row c + dy,
+// cx the ring column of the node
+struct RingAcc {
+    const Ring &R;
+    const int *slot;
+    int cx;
+    __device__ float psi(int k, int dx, int dy) const { return R.psi[k][slot[dy + HALO]][cx + dx]; }
+    __device__ float rho(int k, int dx, int dy) const { return R.rho[k][slot[dy + HALO]][cx + dx]; }
+};
 
 // Momentum sum_i f_i e_i of one component as antisymmetric differences.
 __device__ __forceinline__ void mom9(const float f[9], float &mx, float &my)

@@ -17,26 +17,28 @@ enum ResSlot {
 // device-side tables of a context (all inside the caller's workspace)
 struct Dev {
     KInst *insts;   // [ninst]
-    int4 *tiles;    // [ntiles] {inst, x0, y0, 0}
+    int4 *tiles;    // [ntiles] {inst, x0, y0, 0}: 2-D tiles of the auxiliary kernels
+    int4 *strips;   // [nstrips] {inst, X0, Y0, wo | ho << 16}: work of the fused step
     int2 *rows;     // [nrows]  {inst, y}
     int *row0s;     // [ninst]  first row index of each instance in rows
     double *part;   // [nrows][NQR]
     double *res;    // [ninst][NRES]
-    int ninst, ntiles, nrows;
+    int ninst, ntiles, nrows, nstrips;
 };
 
 hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
 hipError_t launch_step(const Dev &d, int par, hipStream_t st);
+hipError_t launch_density(const Dev &d, int par, hipStream_t st);
 hipError_t launch_fields(const Dev &d, int par, hipStream_t st);
 hipError_t launch_fields_out(const Dev &d, int inst, float *rho, float *u, hipStream_t st);
 hipError_t launch_export(const Dev &d, int inst, int par, float *f, hipStream_t st);
 hipError_t launch_import(const Dev &d, int inst, int par, const float *f, hipStream_t st);
-hipError_t launch_forces(const Dev &d, int inst, const float *rho, float *F, hipStream_t st);
+hipError_t launch_forces(const Dev &d, int inst, int par, const float *rho, float *F, hipStream_t st);
 hipError_t launch_observables(const Dev &d, int par, double margin, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t st);
 
 // kernels of one step, for timing: number, names, and a launcher of kernel j
-constexpr int N_STEP_KERNELS = 2;
+constexpr int N_STEP_KERNELS = 1;
 const char *step_kernel_name(int j);
 hipError_t launch_step_kernel(const Dev &d, int j, int par, hipStream_t st);
 

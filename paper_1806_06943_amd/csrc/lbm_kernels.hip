@@ -1,16 +1,14 @@
 // HIP kernels of the two-range pseudopotential LBM step on gfx950
-// (arXiv:1806.06943, Sec. II).  Every kernel walks a flat table of tiles
-// (instance, x0, y0) or rows (instance, y), so one launch covers one lattice
+// (arXiv:1806.06943, Sec. II).  Every kernel walks a flat table of strips,
+// tiles or rows tagged with their instance, so one launch covers one lattice
 // or many lattices of different sizes alike.
 #include "lbm_internal.h"
 
 namespace lbm {
 
 // ------------------------------------------------------------------ init
-// Equilibrium at rest, f_{k,i} = w_i rho_k (Eq. 2 with u = 0), written as the
-// post-collision state of the step before: f*_i(x) = f_i(x + e_i, 0), or the
-// node's own value when x + e_i lies beyond a wall.  rho0 holds FP64
-// densities [k][ny][nx] (dense).
+// Equilibrium at rest, f_{k,i} = w_i rho_k (Eq. 2 with u = 0), from FP64
+// densities rho0s[inst][k][ny][nx] (dense), rounded once to FP32 deviations.
 __global__ __launch_bounds__(NTHREADS) void k_init(const KInst *__restrict__ insts,
                                                     const int4 *__restrict__ tiles,
                                                     const double *const *__restrict__ rho0s,
@@ -23,28 +21,20 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const KInst *__restrict__ ins
     if (x >= P.nx || y >= P.ny) return;
     const double *rho0 = rho0s[t.x];
     const int64_t N = (int64_t)P.nx * P.ny;
-    constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     constexpr double CI[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
     float *out = P.f[par];
-    for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < 9; ++i) {
-            int xs = wrapi(x + EX[i], P.nx);
-            int ys = y + EY[i];
-            if (P.walls && (ys < 0 || ys >= P.ny)) {
-                xs = x;
-                ys = y;
-            } else {
-                ys = wrapi(ys, P.ny);
-            }
-            const double r = rho0[k * N + (int64_t)ys * P.nx + xs];
-            out[(int64_t)(k * 9 + i) * P.plane + (int64_t)y * P.pitch + x] =
+    const int64_t o = (int64_t)y * P.pitch + x;
+    for (int k = 0; k < 2; ++k) {
+        const double r = rho0[k * N + (int64_t)y * P.nx + x];
+        for (int i = 0; i < 9; ++i)
+            out[(int64_t)(k * 9 + i) * P.plane + o] =
                 (float)(CI[i] / 36.0 * (r - (double)P.rho_ref[k]));
-        }
+    }
 }
 
 // ------------------------------------------------------------------ density pass
-// rho_k(x) = rho_ref + sum_i f_i(x) (Eq. 6) for the pre-collision state.
+// rho_k(x) = rho_ref + sum_i f_i(x) (Eq. 6) of the state in buffer par; the
+// fused step writes the same quantity for the next state itself.
 __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ insts,
                                                        const int4 *__restrict__ tiles, int par)
 {
@@ -54,57 +44,200 @@ __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ 
     const int y = t.z + (int)(threadIdx.x / TX);
     if (x >= P.nx || y >= P.ny) return;
     float f[2][9];
-    gather(P, P.f[par], x, y, f);
+    load_node(P, P.f[par], x, y, f);
     const int64_t o = (int64_t)y * P.pitch + x;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         float hi, lo;
         sum9(f[k], hi, lo);
-        P.rho[k * P.plane + o] = P.rho_ref[k] + (hi + lo);
+        P.rho[par][k * P.plane + o] = P.rho_ref[k] + (hi + lo);
     }
 }
 
-// ------------------------------------------------------------------ step
-// Forces from the LDS density tile, moments, common velocity, BGK + Guo
-// collision, pull streaming: reads f[par], writes f[par ^ 1].
-__global__ __launch_bounds__(NTHREADS) void k_step(const KInst *__restrict__ insts,
-                                                    const int4 *__restrict__ tiles, int par)
+// ------------------------------------------------------------------ fused step
+// One wavefront advances a strip of wo <= 62 output columns [X0, X0 + wo) and
+// ho output rows [Y0, Y0 + ho) by one time step.  Lane l owns lattice column
+// X0 - 1 + l; lanes 0 and wo + 1 are the one-column halo whose collision the
+// neighbouring strips also compute.  The wavefront marches down the rows:
+//   * an LDS ring holds rho and psi of rows c-2 .. c+2 (columns X0-3 .. X0+64)
+//     for the force stencil of collided row c;
+//   * collided rows c-2 (upward populations) and c-1 (all) stay in registers;
+//   * output row o = c - 1 pulls f_i(x, o) = f*_i(x - e_i) from rows o-1, o,
+//     o+1, the x shift by one lane done with cross-lane shuffles, bounce-back
+//     from the node itself next to a wall;
+//   * f(t+1) and rho(t+1) of the output row are written aligned.
+// Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
+__global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ insts,
+                                                    const int4 *__restrict__ strips, int par)
 {
-    __shared__ Tile T;
-    const int4 t = tiles[blockIdx.x];
+    __shared__ Ring R;
+    const int4 t = strips[blockIdx.x];
     const KInst &P = insts[t.x];
-    stage_tile(P, t.y, t.z, T);
-    __syncthreads();
-    const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
-    const int x = t.y + lx, y = t.z + ly;
-    if (x >= P.nx || y >= P.ny) return;
+    const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = t.w >> 16;
+    const int l = (int)threadIdx.x;
+    const int nx = P.nx, ny = P.ny, walls = P.walls;
+    const int64_t pl = P.plane;
+    const int pitch = P.pitch;
+    const int xc = wrapi(X0 - 1 + l, nx);
+    const bool coll = l < wo + 2;
+    const bool outl = (l >= 1) && (l <= wo);
+    const float *__restrict__ fin = P.f[par];
+    float *__restrict__ fout = P.f[par ^ 1];
+    const float *__restrict__ rin = P.rho[par];
+    float *__restrict__ rout = P.rho[par ^ 1];
+    // ring column j holds lattice column X0 - 1 - HALO + j; lane l fills
+    // j = l and, for l < RW - SW, j = SW + l
+    const int gx0 = wrapi(X0 - 1 - HALO + l, nx);
+    const int gx1 = wrapi(X0 - 1 - HALO + SW + l, nx);
+    const bool extra = l < RW - SW;
 
-    float f[2][9];
-    gather(P, P.f[par], x, y, f);
-    float F[2][2];
-    tile_force(P, T, lx + HALO, ly + HALO, F);
-
-    float dh[2], dl[2], rho[2], jx[2], jy[2];
+    auto rowok = [&](int r) { return !walls || (r >= 0 && r < ny); };
+    auto ring_load = [&](int r, float v[2][2]) {
+        if (!rowok(r)) {
+            v[0][0] = v[0][1] = P.rho_wall[0];
+            v[1][0] = v[1][1] = P.rho_wall[1];
+        } else {
+            const int64_t ro = (int64_t)wrapi(r, ny) * pitch;
+            for (int k = 0; k < 2; ++k) {
+                v[k][0] = rin[k * pl + ro + gx0];
+                v[k][1] = extra ? rin[k * pl + ro + gx1] : 0.0f;
+            }
+        }
+    };
+    auto ring_store = [&](int slot, int r, const float v[2][2]) {
+        const bool wall = !rowok(r);
+        for (int k = 0; k < 2; ++k) {
+            R.rho[k][slot][l] = v[k][0];
+            R.psi[k][slot][l] = wall ? P.psi_wall[k] : psi_of(P, v[k][0]);
+            if (extra) {
+                R.rho[k][slot][SW + l] = v[k][1];
+                R.psi[k][slot][SW + l] = wall ? P.psi_wall[k] : psi_of(P, v[k][1]);
+            }
+        }
+    };
+    auto load_f = [&](int r, float f[2][9]) {
+        if (coll && rowok(r)) {
+            load_node(P, fin, xc, wrapi(r, ny), f);
+        } else {
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        sum9(f[k], dh[k], dl[k]);
-        rho[k] = T.rho[k][ly + HALO][lx + HALO];
-        float mx, my;
-        mom9(f[k], mx, my);
-        jx[k] = mx + 0.5f * F[k][0];
-        jy[k] = my + 0.5f * F[k][1];
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[k][i] = 0.0f;
+        }
+    };
+    // ring slot of lattice row r (r >= Y0 - 3)
+    auto slot_of = [&](int r) { return (r - Y0 + 1 + HALO) % RR; };
+
+    for (int q = 0; q < RR; ++q) {
+        float v[2][2];
+        ring_load(Y0 - 1 - HALO + q, v);
+        ring_store(q, Y0 - 1 - HALO + q, v);
     }
-    float ux, uy;
-    common_velocity(P, rho, jx, jy, ux, uy);
+    __syncthreads();
 
-    float *out = P.f[par ^ 1];
-    const int64_t o = (int64_t)y * P.pitch + x;
+    float fn[2][9];
+    load_f(Y0 - 1, fn);
+    float Sprev[2][9], Uprev[2][3];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        float post[9];
-        collide(P, k, f[k], dh[k], dl[k], rho[k], F[k][0], F[k][1], ux, uy, post);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out[(int64_t)(k * 9 + i) * P.plane + o] = post[i];
+        for (int i = 0; i < 9; ++i) Sprev[k][i] = 0.0f;
+        Uprev[k][0] = Uprev[k][1] = Uprev[k][2] = 0.0f;
+    }
+
+    const int nit = ho + 2;
+    for (int it = 0; it < nit; ++it) {
+        const int c = Y0 - 1 + it;
+        const bool more = it + 1 < nit;
+        float f[2][9];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[k][i] = fn[k][i];
+        // prefetch the next collided row and the next density row
+        if (more) load_f(c + 1, fn);
+        float vnext[2][2];
+        if (more) ring_load(c + 3, vnext);
+
+        // collide row c
+        float S[2][9];
+        if (rowok(c)) {
+            int slot[RR];
+#pragma unroll
+            for (int d = 0; d < RR; ++d) slot[d] = slot_of(c - HALO + d);
+            float F[2][2];
+            stencil_force(P, RingAcc{R, slot, l + HALO}, F);
+            float dh[2], dl[2], rho[2], jx[2], jy[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                sum9(f[k], dh[k], dl[k]);
+                rho[k] = R.rho[k][slot[HALO]][l + HALO];
+                float mx, my;
+                mom9(f[k], mx, my);
+                jx[k] = mx + 0.5f * F[k][0];
+                jy[k] = my + 0.5f * F[k][1];
+            }
+            float ux, uy;
+            common_velocity(P, rho, jx, jy, ux, uy);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                collide(P, k, f[k], dh[k], dl[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) S[k][i] = 0.0f;
+        }
+
+        // stream into output row o = c - 1
+        if (it >= 2) {
+            const int o = c - 1;
+            const bool wlo = walls && o == 0;
+            const bool whi = walls && o == ny - 1;
+            float g[2][9];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const float h1 = __shfl_up(Sprev[k][1], 1);
+                const float h3 = __shfl_down(Sprev[k][3], 1);
+                const float u5 = __shfl_up(Uprev[k][1], 1);
+                const float u6 = __shfl_down(Uprev[k][2], 1);
+                const float d7 = __shfl_down(S[k][7], 1);
+                const float d8 = __shfl_up(S[k][8], 1);
+                g[k][0] = Sprev[k][0];
+                g[k][1] = h1;
+                g[k][3] = h3;
+                g[k][2] = wlo ? Sprev[k][4] : Uprev[k][0];
+                g[k][5] = wlo ? Sprev[k][7] : u5;
+                g[k][6] = wlo ? Sprev[k][8] : u6;
+                g[k][4] = whi ? Sprev[k][2] : S[k][4];
+                g[k][7] = whi ? Sprev[k][5] : d7;
+                g[k][8] = whi ? Sprev[k][6] : d8;
+            }
+            if (outl) {
+                const int64_t oo = (int64_t)o * pitch + (X0 - 1 + l);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) fout[(int64_t)(k * 9 + i) * pl + oo] = g[k][i];
+                    float hi, lo;
+                    sum9(g[k], hi, lo);
+                    rout[k * pl + oo] = P.rho_ref[k] + (hi + lo);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            Uprev[k][0] = Sprev[k][2];
+            Uprev[k][1] = Sprev[k][5];
+            Uprev[k][2] = Sprev[k][6];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Sprev[k][i] = S[k][i];
+        }
+        if (more) {
+            __syncthreads();  // every lane has read the ring row about to be replaced
+            ring_store(slot_of(c + 1 + HALO), c + 1 + HALO, vnext);
+            __syncthreads();
+        }
     }
 }
 
@@ -117,13 +250,13 @@ __global__ __launch_bounds__(NTHREADS) void k_fields(const KInst *__restrict__ i
     __shared__ Tile T;
     const int4 t = tiles[blockIdx.x];
     const KInst &P = insts[t.x];
-    stage_tile(P, t.y, t.z, T);
+    stage_tile(P, P.rho[par], t.y, t.z, T);
     __syncthreads();
     const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
     const int x = t.y + lx, y = t.z + ly;
     if (x >= P.nx || y >= P.ny) return;
     float f[2][9];
-    gather(P, P.f[par], x, y, f);
+    load_node(P, P.f[par], x, y, f);
     float F[2][2];
     tile_force(P, T, lx + HALO, ly + HALO, F);
     float rho[2], mxs = 0.f, mys = 0.f, jxs = 0.f, jys = 0.f;
@@ -186,15 +319,11 @@ __global__ __launch_bounds__(NTHREADS) void k_export(const KInst *__restrict__ i
     const int x = t.y + (int)(threadIdx.x % TX);
     const int y = t.z + (int)(threadIdx.x / TX);
     if (x >= P.nx || y >= P.ny) return;
-    float f[2][9];
-    gather(P, P.f[par], x, y, f);
     const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
-    for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < 9; ++i) fout[(int64_t)(k * 9 + i) * N + n] = f[k][i];
+    const int64_t o = (int64_t)y * P.pitch + x;
+    for (int j = 0; j < 18; ++j) fout[(int64_t)j * N + n] = P.f[par][(int64_t)j * P.plane + o];
 }
 
-// Inverse of k_export: pre-collision f(x) -> post-collision storage
-// f*_i(x) = f_i(x + e_i), or f_opp(i)(x) when x + e_i lies beyond a wall.
 __global__ __launch_bounds__(NTHREADS) void k_import(const KInst *__restrict__ insts,
                                                       const int4 *__restrict__ tiles, int inst,
                                                       int par, const float *__restrict__ fin)
@@ -205,28 +334,14 @@ __global__ __launch_bounds__(NTHREADS) void k_import(const KInst *__restrict__ i
     const int x = t.y + (int)(threadIdx.x % TX);
     const int y = t.z + (int)(threadIdx.x / TX);
     if (x >= P.nx || y >= P.ny) return;
-    constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-    const int64_t N = (int64_t)P.nx * P.ny;
-    float *out = P.f[par];
-    for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < 9; ++i) {
-            int xs = wrapi(x + EX[i], P.nx), ys = y + EY[i], ii = i;
-            if (P.walls && (ys < 0 || ys >= P.ny)) {
-                xs = x;
-                ys = y;
-                ii = OPP[i];
-            } else {
-                ys = wrapi(ys, P.ny);
-            }
-            out[(int64_t)(k * 9 + i) * P.plane + (int64_t)y * P.pitch + x] =
-                fin[(int64_t)(k * 9 + ii) * N + (int64_t)ys * P.nx + xs];
-        }
+    const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
+    const int64_t o = (int64_t)y * P.pitch + x;
+    for (int j = 0; j < 18; ++j) P.f[par][(int64_t)j * P.plane + o] = fin[(int64_t)j * N + n];
 }
 
 // ------------------------------------------------------------------ forces only
-__global__ void k_rho_in(const KInst *__restrict__ insts, int inst, const float *rho_in)
+// densities of lbm_forces go to rho[par ^ 1], which the next step overwrites
+__global__ void k_rho_in(const KInst *__restrict__ insts, int inst, int par, const float *rho_in)
 {
     const KInst &P = insts[inst];
     const int64_t N = (int64_t)P.nx * P.ny;
@@ -235,19 +350,19 @@ __global__ void k_rho_in(const KInst *__restrict__ insts, int inst, const float 
         const int k = (int)(n / N);
         const int64_t m = n % N;
         const int y = (int)(m / P.nx), x = (int)(m % P.nx);
-        P.rho[k * P.plane + (int64_t)y * P.pitch + x] = rho_in[n];
+        P.rho[par ^ 1][k * P.plane + (int64_t)y * P.pitch + x] = rho_in[n];
     }
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_forces(const KInst *__restrict__ insts,
                                                       const int4 *__restrict__ tiles, int inst,
-                                                      float *__restrict__ Fout)
+                                                      int par, float *__restrict__ Fout)
 {
     __shared__ Tile T;
     const int4 t = tiles[blockIdx.x];
     if (t.x != inst) return;  // uniform per block: no thread reaches the barrier below
     const KInst &P = insts[t.x];
-    stage_tile(P, t.y, t.z, T);
+    stage_tile(P, P.rho[par ^ 1], t.y, t.z, T);
     __syncthreads();
     const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
     const int x = t.y + lx, y = t.z + ly;
@@ -311,7 +426,7 @@ __global__ __launch_bounds__(RT) void k_red_rows1(const KInst *__restrict__ inst
     double amax = -INFINITY, amin = INFINITY, bad = 0;
     for (int x = threadIdx.x; x < P.nx; x += RT) {
         float f[2][9];
-        gather(P, P.f[par], x, y, f);
+        load_node(P, P.f[par], x, y, f);
         for (int i = 0; i < 9; ++i) {
             mA += (double)f[0][i];
             mB += (double)f[1][i];
@@ -585,39 +700,40 @@ hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st)
 {
     k_init<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, rho0s, 0);
     LAUNCH_CHECK();
+    k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, 0);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_density(const Dev &d, int par, hipStream_t st)
+{
+    k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
+    LAUNCH_CHECK();
     return hipSuccess;
 }
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)
 {
-    k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
-    LAUNCH_CHECK();
-    k_step<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
+    k_fused_step<<<d.nstrips, SW, 0, st>>>(d.insts, d.strips, par);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
 const char *step_kernel_name(int j)
 {
-    static const char *names[N_STEP_KERNELS] = {"k_density", "k_step"};
+    static const char *names[N_STEP_KERNELS] = {"k_fused_step"};
     return (j >= 0 && j < N_STEP_KERNELS) ? names[j] : "";
 }
 
-// kernel j of the step alone; neither changes the state of buffer par
+// kernel j of the step alone; it writes only the buffers of the next state
 hipError_t launch_step_kernel(const Dev &d, int j, int par, hipStream_t st)
 {
-    if (j == 0)
-        k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
-    else
-        k_step<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
-    LAUNCH_CHECK();
-    return hipSuccess;
+    (void)j;
+    return launch_step(d, par, st);
 }
 
 hipError_t launch_fields(const Dev &d, int par, hipStream_t st)
 {
-    k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
-    LAUNCH_CHECK();
     k_fields<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
     LAUNCH_CHECK();
     return hipSuccess;
@@ -641,14 +757,16 @@ hipError_t launch_import(const Dev &d, int inst, int par, const float *f, hipStr
 {
     k_import<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, inst, par, f);
     LAUNCH_CHECK();
+    k_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, par);
+    LAUNCH_CHECK();
     return hipSuccess;
 }
 
-hipError_t launch_forces(const Dev &d, int inst, const float *rho, float *F, hipStream_t st)
+hipError_t launch_forces(const Dev &d, int inst, int par, const float *rho, float *F, hipStream_t st)
 {
-    k_rho_in<<<1024, 256, 0, st>>>(d.insts, inst, rho);
+    k_rho_in<<<1024, 256, 0, st>>>(d.insts, inst, par, rho);
     LAUNCH_CHECK();
-    k_forces<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, inst, F);
+    k_forces<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, inst, par, F);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_copy_probe.argtypes = [vp, vp, vp, ctypes.c_uint64]
         L.lbm_profile_step.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double),
                                        P(ctypes.c_char_p), P(ctypes.c_int32)]
+        L.lbm_set_tiling.argtypes = [vp, ctypes.c_int32]
+        L.lbm_get_tiling.argtypes = [vp]
+        L.lbm_get_tiling.restype = ctypes.c_int32
         L.lbm_destroy.argtypes = [vp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
@@ -189,6 +192,14 @@ def lbm_profile_step(ctx, nrep: int, max_k: int = 8):
     _check(lib().lbm_profile_step(ctx, int(nrep), max_k, ms, names, ctypes.byref(nk)), ctx)
     n = min(nk.value, max_k)
     return [(names[j].decode(), ms[j]) for j in range(n)]
+
+
+def lbm_set_tiling(ctx, chunk_rows: int):
+    _check(lib().lbm_set_tiling(ctx, int(chunk_rows)), ctx)
+
+
+def lbm_get_tiling(ctx) -> int:
+    return int(lib().lbm_get_tiling(ctx))
 
 
 def lbm_destroy(ctx):

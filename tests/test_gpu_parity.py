@@ -244,3 +244,40 @@ def test_spinodal_full_size_sampled_nodes(torch):
     obs1, _ = sim.observables()
     for k in range(2):
         assert abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] < 1e-6
+
+
+# ---------------------------------------------------------------- geometry edge cases
+@pytest.mark.parametrize("nx,ny,walls", [(4, 4, 0), (5, 3, 0), (1, 8, 0), (3, 7, 1), (70, 3, 0),
+                                         (63, 5, 1), (125, 9, 0), (2, 1, 0)])
+def test_small_and_ragged_lattices(torch, nx, ny, walls):
+    """Lattices narrower than a strip (offsets alias), one-column and one-row tori,
+    walls on a few rows, ragged strip widths: 40 steps against the oracle."""
+    say("small lattice", nx, ny, walls)
+    r = np.random.default_rng(nx * 100 + ny)
+    rhoA = 0.5 + r.uniform(-0.2, 0.2, size=(ny, nx))
+    rhoB = 0.5 + r.uniform(-0.2, 0.2, size=(ny, nx))
+    inst = dict(nx=nx, ny=ny, rhoA=rhoA, rhoB=rhoB, G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.7),
+                walls=walls, rho_wall=(0.3, 0.6), g=((1e-4, 2e-5), (1e-4, 2e-5)))
+    sim = lbm.Sim([inst])
+    sim.step(40)
+    p = O.Params(nx=nx, ny=ny, G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.7), walls=walls,
+                 rho_wall=(0.3, 0.6), g=((1e-4, 2e-5), (1e-4, 2e-5)))
+    fo = O.run(p, O.init(p, rhoA, rhoB), 40)
+    got = sim.populations_full()
+    assert rel(got, fo) < 1e-6
+    assert np.abs(got - fo).max() < 1e-6
+
+
+def test_strip_height_does_not_change_results(torch):
+    """The strip height only moves work between wavefronts: results are bitwise equal."""
+    w = W.emulsion(nx=200, ny=96, ndrop=4, radius=9, gx=1e-5)
+    ref = None
+    for h in (4, 7, 16, 40, 96):
+        sim = lbm.Sim([lbm.workload_instance(w)])
+        lbm.lbm_set_tiling(sim.ctx, h)
+        assert lbm.lbm_get_tiling(sim.ctx) == h
+        sim.step(35)
+        f = sim.populations().cpu().numpy()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), h
