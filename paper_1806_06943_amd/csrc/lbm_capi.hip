@@ -24,18 +24,22 @@ uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 struct InstLayout {
     int32_t pitch;
-    int64_t plane;       // floats
-    uint64_t bytes;      // per-instance bytes (f0, f1, rho, fld)
+    int64_t plane;       // floats per field plane
+    int64_t fsize;       // floats per population buffer
+    int64_t rsize;       // floats per density buffer
+    uint64_t bytes;      // per-instance bytes (f0, f1, rho0, rho1, fields)
 };
 
 InstLayout inst_layout(const lbm_params &p)
 {
     InstLayout L;
     L.pitch = (int32_t)align_up((uint64_t)p.nx, 64);
-    // pad each plane so that consecutive planes do not sit at the same offset
-    // modulo large powers of two
+    // buffers end on a 256-byte boundary plus 64 floats, so that consecutive
+    // buffers do not sit at the same offset modulo large powers of two
     L.plane = (int64_t)align_up((uint64_t)p.ny * L.pitch, 64) + 64;
-    L.bytes = align_up((uint64_t)(18 + 18 + 2 + 2 + NFLD) * L.plane * sizeof(float), ALIGN);
+    L.fsize = (int64_t)align_up((uint64_t)18 * p.ny * L.pitch, 64) + 64;
+    L.rsize = (int64_t)align_up((uint64_t)2 * p.ny * L.pitch, 64) + 64;
+    L.bytes = align_up((uint64_t)(2 * L.fsize + 2 * L.rsize + NFLD * L.plane) * sizeof(float), ALIGN);
     return L;
 }
 
@@ -129,7 +133,9 @@ std::string check_params(const lbm_params &p)
         snprintf(buf, sizeof buf, "lattice size must be >= 1 (got %d x %d)", p.nx, p.ny);
         return buf;
     }
-    if ((int64_t)p.nx * p.ny > (int64_t)1 << 30) return "lattice larger than 2^30 nodes";
+    // byte offsets inside a population buffer must stay below 2^31
+    if ((uint64_t)inst_layout(p).fsize * sizeof(float) >= ((uint64_t)1 << 31))
+        return "lattice too large: a population buffer must stay below 2 GiB";
     if (p.walls != 0 && p.walls != 1) return "walls must be 0 or 1";
     if (p.reserved != 0) return "reserved field must be 0";
     const double *d = &p.G_AB;
@@ -150,10 +156,10 @@ KInst make_kinst(const lbm_params &p, const InstLayout &L, char *base)
     std::memset(&K, 0, sizeof K);
     float *b = (float *)base;
     K.f[0] = b;
-    K.f[1] = b + 18 * L.plane;
-    K.rho[0] = b + 36 * L.plane;
-    K.rho[1] = b + 38 * L.plane;
-    K.fld = b + 40 * L.plane;
+    K.f[1] = b + L.fsize;
+    K.rho[0] = b + 2 * L.fsize;
+    K.rho[1] = b + 2 * L.fsize + L.rsize;
+    K.fld = b + 2 * L.fsize + 2 * L.rsize;
     K.plane = L.plane;
     K.nx = p.nx;
     K.ny = p.ny;

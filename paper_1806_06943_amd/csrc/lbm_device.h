@@ -3,8 +3,16 @@
 // gather, the two-belt force from an LDS density tile and the FP32 collision.
 //
 // Storage: the state at time t is the post-streaming, pre-collision
-// populations f(t) as FP32 deviations f - w_i rho_ref, plus the densities
-// rho(t) (double-buffered with rho(t+1)).
+// populations f(t) as FP32 deviations f - w_i rho_ref, plus their density
+// deviations sum_i (f_i - w_i rho_ref), correctly rounded from the exact sum
+// (double-buffered with those of t+1).  The collision needs exactly that
+// rounded sum, so the step reads it instead of summing again.
+//
+// Layout: row-major rows of population segments, f[y][q][x] with q = 9 k + i
+// and a row segment of `pitch` floats (x fastest), and likewise rho[y][k][x].
+// A wavefront working on one lattice row touches one contiguous block of
+// 18 segments, and the wavefronts of neighbouring strips share it: DRAM
+// pages are reused instead of 36 planes megabytes apart being streamed.
 //
 // Numerical formulation (FP32 throughout the step):
 //   * the density deviation sum uses error-free TwoSum accumulation, so the
@@ -41,10 +49,10 @@ enum FieldPlane { FLD_RHOA = 0, FLD_RHOB, FLD_UX, FLD_UY, FLD_PB, FLD_MX, FLD_MY
 
 // Launch parameters of one instance (device copy lives in the workspace).
 struct KInst {
-    float *f[2];           // population buffers [k][i] planes of ny rows x pitch floats
-    float *rho[2];         // density buffers [k] planes, paired with f[]
-    float *fld;            // field scratch planes [NFLD]
-    int64_t plane;         // floats between consecutive planes of f, rho and fld
+    float *f[2];           // population buffers f[y][q][x], paired with rho[]
+    float *rho[2];         // density-deviation buffers rho[y][k][x]
+    float *fld;            // field scratch planes [NFLD][ny][pitch]
+    int64_t plane;         // floats between consecutive field planes
     int32_t nx, ny, pitch, walls;
     float cw[2][5];        // merged Eq. 8 weights G1 w + G2 p per |e|^2 in {1, 2, 4, 5, 8}
     float gr1, gr2;        // Eq. 9 weights G_AB w(1), G_AB w(2)
@@ -59,6 +67,36 @@ struct KInst {
     int32_t pad_;
 };
 
+// The arithmetic parameters of an instance, as plain values: kernels that
+// loop over rows copy them once (a reference into global memory would be
+// reloaded after every store).
+struct KPar {
+    float cw[2][5], gr1, gr2, g[2][2], it[2], cf[2], rho_ref[2], rho_wall[2], psi_wall[2];
+    float rho0, inv_rho0;
+};
+
+__device__ __forceinline__ KPar kpar(const KInst &P)
+{
+    KPar q;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q.cw[k][c] = P.cw[k][c];
+        q.g[k][0] = P.g[k][0];
+        q.g[k][1] = P.g[k][1];
+        q.it[k] = P.it[k];
+        q.cf[k] = P.cf[k];
+        q.rho_ref[k] = P.rho_ref[k];
+        q.rho_wall[k] = P.rho_wall[k];
+        q.psi_wall[k] = P.psi_wall[k];
+    }
+    q.gr1 = P.gr1;
+    q.gr2 = P.gr2;
+    q.rho0 = P.rho0;
+    q.inv_rho0 = P.inv_rho0;
+    return q;
+}
+
 __device__ __forceinline__ int wrapi(int a, int n)
 {
     if (a >= 0 && a < n) return a;
@@ -67,9 +105,22 @@ __device__ __forceinline__ int wrapi(int a, int n)
 }
 
 // psi = rho0 (1 - exp(-rho/rho0)), through expm1f for accuracy at small rho
-__device__ __forceinline__ float psi_of(const KInst &P, float r)
+template <class Par>
+__device__ __forceinline__ float psi_of(const Par &P, float r)
 {
     return -P.rho0 * expm1f(-r * P.inv_rho0);
+}
+
+// index of population q = 9 k + i of node (x, y) in a population buffer
+__device__ __forceinline__ int64_t fidx(const KInst &P, int q, int x, int y)
+{
+    return ((int64_t)y * 18 + q) * P.pitch + x;
+}
+
+// index of the density deviation of component k of node (x, y)
+__device__ __forceinline__ int64_t ridx(const KInst &P, int k, int x, int y)
+{
+    return ((int64_t)y * 2 + k) * P.pitch + x;
 }
 
 // Populations of node (x, y) from buffer fb (D2Q9 order 0:(0,0) 1:(1,0)
@@ -77,11 +128,10 @@ __device__ __forceinline__ float psi_of(const KInst &P, float r)
 __device__ __forceinline__ void load_node(const KInst &P, const float *__restrict__ fb, int x,
                                           int y, float f[2][9])
 {
-    const int64_t o = (int64_t)y * P.pitch + x;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[k][i] = fb[(int64_t)(k * 9 + i) * P.plane + o];
+        for (int i = 0; i < 9; ++i) f[k][i] = fb[fidx(P, k * 9 + i, x, y)];
 }
 
 // Error-free sum of the nine deviations: drho = hi + lo exactly up to the
@@ -109,11 +159,11 @@ struct Tile {
 
 // Fill the LDS tile for the tile whose first node is (x0, y0).  Periodic wrap
 // in x (and in y without walls); rows beyond a wall hold the wall densities.
+// rb holds density deviations (absolute = false) or densities.
 __device__ __forceinline__ void stage_tile(const KInst &P, const float *__restrict__ rb, int x0,
-                                           int y0, Tile &T)
+                                           int y0, Tile &T, bool absolute = false)
 {
     constexpr int W = TX + 2 * HALO, H = TY + 2 * HALO;
-    const int64_t pl = P.plane;
     for (int t = threadIdx.x; t < W * H; t += NTHREADS) {
         const int lx = t % W, ly = t / W;
         const int gx = wrapi(x0 + lx - HALO, P.nx);
@@ -126,9 +176,9 @@ __device__ __forceinline__ void stage_tile(const KInst &P, const float *__restri
             pB = P.psi_wall[1];
         } else {
             gy = wrapi(gy, P.ny);
-            const int64_t o = (int64_t)gy * P.pitch + gx;
-            rA = rb[o];
-            rB = rb[pl + o];
+            const float dA = rb[ridx(P, 0, gx, gy)], dB = rb[ridx(P, 1, gx, gy)];
+            rA = absolute ? dA : P.rho_ref[0] + dA;
+            rB = absolute ? dB : P.rho_ref[1] + dB;
             pA = psi_of(P, rA);
             pB = psi_of(P, rB);
         }
@@ -143,8 +193,8 @@ __device__ __forceinline__ void stage_tile(const KInst &P, const float *__restri
 // acc.psi(k, dx, dy) and acc.rho(k, dx, dy) give the values at the node
 // displaced by (dx, dy).  F^c (Eq. 8) with merged weights, F^r (Eq. 9),
 // F^b = rho g.
-template <class Acc>
-__device__ __forceinline__ void stencil_force(const KInst &P, const Acc &acc, float F[2][2])
+template <class Par, class Acc>
+__device__ __forceinline__ void stencil_force(const Par &P, const Acc &acc, float F[2][2])
 {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -204,6 +254,7 @@ __device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx
 struct Ring {
     float rho[2][RR][RW];
     float psi[2][RR][RW];
+    float dev[2][RR][RW];  // density deviations (own-node term of the collision)
 };
 
 // accessor into the ring: slot[dy + 2] is the ring row of lattice row c + dy,
@@ -223,45 +274,77 @@ __device__ __forceinline__ void mom9(const float f[9], float &mx, float &my)
     my = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
 }
 
+// x / 36 correctly rounded in the usual case, from a product and one FMA
+// correction (the residual x - 36 q is exact): an unbiased scaling, unlike a
+// product with the rounded constant 1/36, whose error has a fixed sign.
+__device__ __forceinline__ float div36(float x)
+{
+    const float q = x * (1.0f / 36.0f);
+    const float r = fmaf(-36.0f, q, x);
+    return fmaf(r, 1.0f / 36.0f, q);
+}
+
+// 1 / d from the hardware reciprocal refined by one Newton step
+__device__ __forceinline__ float recip(float d)
+{
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float e = fmaf(-d, r, 1.0f);
+    return fmaf(e, r, r);
+}
+
 // Common velocity u^eq of Eq. 3 from the component momenta j_k (with F/2).
-__device__ __forceinline__ void common_velocity(const KInst &P, const float rho[2],
+template <class Par>
+__device__ __forceinline__ void common_velocity(const Par &P, const float rho[2],
                                                 const float jx[2], const float jy[2], float &ux,
                                                 float &uy)
 {
-    const float den = rho[0] * P.it[0] + rho[1] * P.it[1];
-    ux = (jx[0] * P.it[0] + jx[1] * P.it[1]) / den;
-    uy = (jy[0] * P.it[0] + jy[1] * P.it[1]) / den;
+    const float inv = recip(fmaf(rho[0], P.it[0], rho[1] * P.it[1]));
+    ux = fmaf(jx[0], P.it[0], jx[1] * P.it[1]) * inv;
+    uy = fmaf(jy[0], P.it[0], jy[1] * P.it[1]) * inv;
 }
 
 // BGK + Guo collision of one component (Eqs. 1, 2 with the 1/2 on the
 // quadratic term, 5), in deviation form.  f: pre-collision deviations,
-// (dh, dl): their exact sum, rho: density, F: force, (ux, uy): u^eq.
-__device__ __forceinline__ void collide(const KInst &P, int k, const float f[9], float dh,
-                                        float dl, float rho, float Fx, float Fy, float ux,
-                                        float uy, float out[9])
+// drho: their correctly rounded sum, rho: density, F: force, (ux, uy): u^eq.
+// Opposite directions share e.u and e.F: the equilibrium splits into the
+// even part 4.5 (e.u)^2 - 1.5 u.u and the odd part 3 e.u, the Guo bracket
+// into 9 (e.u)(e.F) - 3 u.F and 3 e.F.
+template <class Par>
+__device__ __forceinline__ void collide(const Par &P, int k, const float f[9], float drho,
+                                        float rho, float Fx, float Fy, float ux, float uy,
+                                        float out[9])
 {
-    constexpr float EXf[9] = {0.f, 1.f, 0.f, -1.f, 0.f, 1.f, -1.f, -1.f, 1.f};
-    constexpr float EYf[9] = {0.f, 0.f, 1.f, 0.f, -1.f, 1.f, 1.f, -1.f, -1.f};
-    constexpr float CI[9] = {16.f, 4.f, 4.f, 4.f, 4.f, 1.f, 1.f, 1.f, 1.f};
-    const float a = (dh + dl) / 36.0f;   // rest-state deviation per unit weight
-    const float r36 = rho / 36.0f;
+    const float a = div36(drho);   // rest-state deviation per unit weight
+    const float r36 = div36(rho);
     const float it = P.it[k];
+    const float omit = 1.0f - it;
     const float cf = P.cf[k];
-    const float uu = ux * ux + uy * uy;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const float ex = EXf[i], ey = EYf[i];
-        const float eu = ex * ux + ey * uy;
-        const float q = eu * (3.0f + 4.5f * eu) - 1.5f * uu;
-        const float feqs = CI[i] * (r36 * q);
-        const float eF = ex * Fx + ey * Fy;
-        const float cterm = 3.0f * ((ex - ux) * Fx + (ey - uy) * Fy) + 9.0f * eu * eF;
-        const float C = CI[i] * (cf * cterm);
-        const float rest = CI[i] * a;
-        const float gi = f[i] - rest;
-        const float small = gi + (feqs - gi) * it + C;
-        out[i] = rest + small;
-    }
+    const float uu = fmaf(ux, ux, uy * uy);
+    const float uF = fmaf(ux, Fx, uy * Fy);
+    // relaxation of the small part g = f - c a towards f^eq - c a, plus C
+    auto relax = [&](float fi, float c, float feq_small, float C) {
+        const float rest = c * a;
+        const float g = fi - rest;
+        return rest + fmaf(g, omit, fmaf(feq_small, it, C));
+    };
+    // rest direction: e = 0
+    out[0] = relax(f[0], 16.0f, 16.0f * (r36 * (-1.5f * uu)), 16.0f * (cf * (-3.0f * uF)));
+    // pairs (i, opp(i)) with e_i = (ex, ey) and weight c
+    auto pair = [&](int i, int j, float ex, float ey, float c) {
+        const float eu = fmaf(ex, ux, ey * uy);
+        const float eF = fmaf(ex, Fx, ey * Fy);
+        const float qe = fmaf(4.5f * eu, eu, -1.5f * uu);
+        const float qo = 3.0f * eu;
+        const float ce = fmaf(9.0f * eu, eF, -3.0f * uF);
+        const float co = 3.0f * eF;
+        const float rc = c * r36, fc = c * cf;
+        out[i] = relax(f[i], c, rc * (qe + qo), fc * (ce + co));
+        out[j] = relax(f[j], c, rc * (qe - qo), fc * (ce - co));
+    };
+    pair(1, 3, 1.0f, 0.0f, 4.0f);
+    pair(2, 4, 0.0f, 1.0f, 4.0f);
+    pair(5, 7, 1.0f, 1.0f, 1.0f);
+    pair(6, 8, -1.0f, 1.0f, 1.0f);
 }
 
 }  // namespace lbm

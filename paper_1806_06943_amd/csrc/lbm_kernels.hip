@@ -23,18 +23,17 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const KInst *__restrict__ ins
     const int64_t N = (int64_t)P.nx * P.ny;
     constexpr double CI[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
     float *out = P.f[par];
-    const int64_t o = (int64_t)y * P.pitch + x;
     for (int k = 0; k < 2; ++k) {
         const double r = rho0[k * N + (int64_t)y * P.nx + x];
         for (int i = 0; i < 9; ++i)
-            out[(int64_t)(k * 9 + i) * P.plane + o] =
-                (float)(CI[i] / 36.0 * (r - (double)P.rho_ref[k]));
+            out[fidx(P, k * 9 + i, x, y)] = (float)(CI[i] / 36.0 * (r - (double)P.rho_ref[k]));
     }
 }
 
 // ------------------------------------------------------------------ density pass
-// rho_k(x) = rho_ref + sum_i f_i(x) (Eq. 6) of the state in buffer par; the
-// fused step writes the same quantity for the next state itself.
+// Density deviation sum_i f_i(x) (Eq. 6, deviation form), correctly rounded,
+// of the state in buffer par; the fused step writes the same quantity for
+// the next state itself.
 __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ insts,
                                                        const int4 *__restrict__ tiles, int par)
 {
@@ -45,16 +44,49 @@ __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ 
     if (x >= P.nx || y >= P.ny) return;
     float f[2][9];
     load_node(P, P.f[par], x, y, f);
-    const int64_t o = (int64_t)y * P.pitch + x;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         float hi, lo;
         sum9(f[k], hi, lo);
-        P.rho[par][k * P.plane + o] = P.rho_ref[k] + (hi + lo);
+        P.rho[par][ridx(P, k, x, y)] = hi + lo;
     }
 }
 
 // ------------------------------------------------------------------ fused step
+// Buffer descriptor over one population or density buffer of an instance:
+// accesses are (scalar plane offset, per-lane byte offset) pairs, and the
+// hardware range check returns 0 for (and drops) anything beyond `bytes`.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+}
+
+// FP32 load / store through a buffer descriptor (the b32 builtins move raw bits)
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Lane shifts of a wavefront through DPP (lane l receives lane l - 1, resp.
+// l + 1; the end lanes keep their own value and are never consumed).
+__device__ __forceinline__ float from_left(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float from_right(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
 // One wavefront advances a strip of wo <= 62 output columns [X0, X0 + wo) and
 // ho output rows [Y0, Y0 + ho) by one time step.  Lane l owns lattice column
 // X0 - 1 + l; lanes 0 and wo + 1 are the one-column halo whose collision the
@@ -63,80 +95,112 @@ __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ 
 //     for the force stencil of collided row c;
 //   * collided rows c-2 (upward populations) and c-1 (all) stay in registers;
 //   * output row o = c - 1 pulls f_i(x, o) = f*_i(x - e_i) from rows o-1, o,
-//     o+1, the x shift by one lane done with cross-lane shuffles, bounce-back
+//     o+1, the x shift by one lane done with DPP lane shifts, bounce-back
 //     from the node itself next to a wall;
 //   * f(t+1) and rho(t+1) of the output row are written aligned.
+// The loop body has no lane-divergent branches: every lane loads a valid
+// column (idle lanes a neighbour's), rows beyond a wall read a clamped row
+// whose values are not used, and lanes that must not write give an offset
+// beyond the buffer, which the descriptor's range check drops (buffers stay
+// below 2 GiB, so that offset plus any segment offset cannot wrap into
+// range).  Memory waits are then exact.  The next row's populations are
+// loaded while the current row is collided.
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
 __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ insts,
                                                     const int4 *__restrict__ strips, int par)
 {
     __shared__ Ring R;
     const int4 t = strips[blockIdx.x];
-    const KInst &P = insts[t.x];
+    const KInst &G = insts[t.x];
+    // arithmetic parameters copied once: the buffer stores below could
+    // otherwise alias them
+    const KPar P = kpar(G);
     const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = t.w >> 16;
     const int l = (int)threadIdx.x;
-    const int nx = P.nx, ny = P.ny, walls = P.walls;
-    const int64_t pl = P.plane;
-    const int pitch = P.pitch;
-    const int xc = wrapi(X0 - 1 + l, nx);
-    const bool coll = l < wo + 2;
+    const int nx = G.nx, ny = G.ny, walls = G.walls;
+    const uint32_t qb = (uint32_t)G.pitch * 4u;   // bytes per row segment
+    const uint32_t frowb = 18u * qb;              // bytes per population row
+    const uint32_t rrowb = 2u * qb;               // bytes per density row
+    const __amdgpu_buffer_rsrc_t fin = make_rsrc(G.f[par], (uint32_t)ny * frowb);
+    const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(G.rho[par], (uint32_t)ny * rrowb);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(G.rho[par ^ 1], (uint32_t)ny * rrowb);
+    const uint32_t xcb = (uint32_t)wrapi(X0 - 1 + l, nx) * 4u;  // collided column, bytes
     const bool outl = (l >= 1) && (l <= wo);
-    const float *__restrict__ fin = P.f[par];
-    float *__restrict__ fout = P.f[par ^ 1];
-    const float *__restrict__ rin = P.rho[par];
-    float *__restrict__ rout = P.rho[par ^ 1];
+    constexpr uint32_t DROP = 0x80000000u;  // out-of-range offset: store dropped
     // ring column j holds lattice column X0 - 1 - HALO + j; lane l fills
-    // j = l and, for l < RW - SW, j = SW + l
-    const int gx0 = wrapi(X0 - 1 - HALO + l, nx);
-    const int gx1 = wrapi(X0 - 1 - HALO + SW + l, nx);
-    const bool extra = l < RW - SW;
+    // j = l (both components) and one (extra column, component) pair: lanes
+    // with the same pair load the same value and write it to the same place
+    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + l, nx) * 4u;
+    const int xe = l & 3, ke = (l >> 2) & 1;
+    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + SW + xe, nx) * 4u + (ke ? qb : 0u);
 
-    auto rowok = [&](int r) { return !walls || (r >= 0 && r < ny); };
-    auto ring_load = [&](int r, float v[2][2]) {
-        if (!rowok(r)) {
-            v[0][0] = v[0][1] = P.rho_wall[0];
-            v[1][0] = v[1][1] = P.rho_wall[1];
-        } else {
-            const int64_t ro = (int64_t)wrapi(r, ny) * pitch;
-            for (int k = 0; k < 2; ++k) {
-                v[k][0] = rin[k * pl + ro + gx0];
-                v[k][1] = extra ? rin[k * pl + ro + gx1] : 0.0f;
-            }
-        }
+    // lattice row r -> wrapped row index, or -1 beyond a wall (general
+    // form, used once per cursor); cursors then advance by one row
+    struct Cursor {
+        int r, i;  // lattice row, its index (or -1)
     };
-    auto ring_store = [&](int slot, int r, const float v[2][2]) {
-        const bool wall = !rowok(r);
-        for (int k = 0; k < 2; ++k) {
-            R.rho[k][slot][l] = v[k][0];
-            R.psi[k][slot][l] = wall ? P.psi_wall[k] : psi_of(P, v[k][0]);
-            if (extra) {
-                R.rho[k][slot][SW + l] = v[k][1];
-                R.psi[k][slot][SW + l] = wall ? P.psi_wall[k] : psi_of(P, v[k][1]);
-            }
-        }
+    auto cursor = [&](int r) {
+        if (walls) return Cursor{r, (r >= 0 && r < ny) ? r : -1};
+        return Cursor{r, wrapi(r, ny)};
     };
-    auto load_f = [&](int r, float f[2][9]) {
-        if (coll && rowok(r)) {
-            load_node(P, fin, xc, wrapi(r, ny), f);
-        } else {
+    auto advance = [&](Cursor &q) {
+        ++q.r;
+        if (walls)
+            q.i = (q.r >= 0 && q.r < ny) ? q.r : -1;
+        else
+            q.i = (q.i + 1 == ny) ? 0 : q.i + 1;
+    };
+    struct RingVals {
+        float a, b, e;  // density deviations of A, B at column l; extra-column value
+    };
+    // rows beyond a wall read row 0 (valid memory); ring_store replaces the values
+    auto ring_load = [&](int ri) {
+        const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * rrowb;
+        RingVals v;
+        v.a = bload(rin, ro + gx0b, 0);
+        v.b = bload(rin, ro + gx0b, qb);
+        v.e = bload(rin, ro + gxeb, 0);
+        return v;
+    };
+    auto ring_store = [&](int slot, int ri, const RingVals &v) {
+        const bool wall = ri < 0;
+        const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + v.a;
+        const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + v.b;
+        R.rho[0][slot][l] = ra;
+        R.rho[1][slot][l] = rb;
+        R.psi[0][slot][l] = wall ? P.psi_wall[0] : psi_of(P, ra);
+        R.psi[1][slot][l] = wall ? P.psi_wall[1] : psi_of(P, rb);
+        R.dev[0][slot][l] = v.a;
+        R.dev[1][slot][l] = v.b;
+        const float re = wall ? P.rho_wall[ke] : P.rho_ref[ke] + v.e;
+        R.dev[ke][slot][SW + xe] = v.e;
+        R.rho[ke][slot][SW + xe] = re;
+        R.psi[ke][slot][SW + xe] = wall ? P.psi_wall[ke] : psi_of(P, re);
+    };
+    auto load_f = [&](int ri, float f[2][9]) {
+        const uint32_t off = (uint32_t)(ri < 0 ? 0 : ri) * frowb + xcb;
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int i = 0; i < 9; ++i) f[k][i] = 0.0f;
-        }
+            for (int i = 0; i < 9; ++i) f[k][i] = bload(fin, off, (uint32_t)(k * 9 + i) * qb);
     };
-    // ring slot of lattice row r (r >= Y0 - 3)
-    auto slot_of = [&](int r) { return (r - Y0 + 1 + HALO) % RR; };
 
+    // ring rows Y0 - 3 .. Y0 + 1 into slots 0..4; slot[d] is the slot of row
+    // c - 2 + d for the row c being collided
+    int slot[RR];
+    Cursor cr = cursor(Y0 - 1 - HALO);  // next row to enter the ring
     for (int q = 0; q < RR; ++q) {
-        float v[2][2];
-        ring_load(Y0 - 1 - HALO + q, v);
-        ring_store(q, Y0 - 1 - HALO + q, v);
+        ring_store(q, cr.i, ring_load(cr.i));
+        slot[q] = q;
+        advance(cr);
     }
     __syncthreads();
 
+    Cursor cc = cursor(Y0 - 1);  // row being collided
+    Cursor cf = cc;              // row of the prefetched populations
     float fn[2][9];
-    load_f(Y0 - 1, fn);
+    load_f(cf.i, fn);
     float Sprev[2][9], Uprev[2][3];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -147,82 +211,72 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
 
     const int nit = ho + 2;
     for (int it = 0; it < nit; ++it) {
-        const int c = Y0 - 1 + it;
-        const bool more = it + 1 < nit;
+        // the next density row first, then the next population row (the last
+        // iteration reads rows beyond the strip: valid and unused)
+        const int rnext = cr.i;
+        const RingVals vnext = ring_load(rnext);
         float f[2][9];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[k][i] = fn[k][i];
-        // prefetch the next collided row and the next density row
-        if (more) load_f(c + 1, fn);
-        float vnext[2][2];
-        if (more) ring_load(c + 3, vnext);
+        advance(cf);
+        load_f(cf.i, fn);
 
-        // collide row c
+        // collide row c (a row beyond a wall is collided from clamped data
+        // and never used)
         float S[2][9];
-        if (rowok(c)) {
-            int slot[RR];
-#pragma unroll
-            for (int d = 0; d < RR; ++d) slot[d] = slot_of(c - HALO + d);
+        {
             float F[2][2];
             stencil_force(P, RingAcc{R, slot, l + HALO}, F);
-            float dh[2], dl[2], rho[2], jx[2], jy[2];
+            float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                sum9(f[k], dh[k], dl[k]);
+                drho[k] = R.dev[k][slot[HALO]][l + HALO];
                 rho[k] = R.rho[k][slot[HALO]][l + HALO];
                 float mx, my;
                 mom9(f[k], mx, my);
-                jx[k] = mx + 0.5f * F[k][0];
-                jy[k] = my + 0.5f * F[k][1];
+                jx[k] = fmaf(0.5f, F[k][0], mx);
+                jy[k] = fmaf(0.5f, F[k][1], my);
             }
             float ux, uy;
             common_velocity(P, rho, jx, jy, ux, uy);
 #pragma unroll
             for (int k = 0; k < 2; ++k)
-                collide(P, k, f[k], dh[k], dl[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int i = 0; i < 9; ++i) S[k][i] = 0.0f;
+                collide(P, k, f[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
         }
 
-        // stream into output row o = c - 1
-        if (it >= 2) {
-            const int o = c - 1;
+        // stream into output row o = c - 1; the first two iterations have no
+        // output row yet and write nothing
+        {
+            const int o = cc.r - 1;
             const bool wlo = walls && o == 0;
             const bool whi = walls && o == ny - 1;
-            float g[2][9];
+            const uint32_t off =
+                (outl && it >= 2) ? (uint32_t)o * frowb + (uint32_t)(X0 - 1 + l) * 4u : DROP;
+            const uint32_t roff =
+                (outl && it >= 2) ? (uint32_t)o * rrowb + (uint32_t)(X0 - 1 + l) * 4u : DROP;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const float h1 = __shfl_up(Sprev[k][1], 1);
-                const float h3 = __shfl_down(Sprev[k][3], 1);
-                const float u5 = __shfl_up(Uprev[k][1], 1);
-                const float u6 = __shfl_down(Uprev[k][2], 1);
-                const float d7 = __shfl_down(S[k][7], 1);
-                const float d8 = __shfl_up(S[k][8], 1);
-                g[k][0] = Sprev[k][0];
-                g[k][1] = h1;
-                g[k][3] = h3;
-                g[k][2] = wlo ? Sprev[k][4] : Uprev[k][0];
-                g[k][5] = wlo ? Sprev[k][7] : u5;
-                g[k][6] = wlo ? Sprev[k][8] : u6;
-                g[k][4] = whi ? Sprev[k][2] : S[k][4];
-                g[k][7] = whi ? Sprev[k][5] : d7;
-                g[k][8] = whi ? Sprev[k][6] : d8;
-            }
-            if (outl) {
-                const int64_t oo = (int64_t)o * pitch + (X0 - 1 + l);
+                float g[9];
+                g[0] = Sprev[k][0];
+                g[1] = from_left(Sprev[k][1]);
+                g[3] = from_right(Sprev[k][3]);
+                const float u5 = from_left(Uprev[k][1]);
+                const float u6 = from_right(Uprev[k][2]);
+                const float d7 = from_right(S[k][7]);
+                const float d8 = from_left(S[k][8]);
+                g[2] = wlo ? Sprev[k][4] : Uprev[k][0];
+                g[5] = wlo ? Sprev[k][7] : u5;
+                g[6] = wlo ? Sprev[k][8] : u6;
+                g[4] = whi ? Sprev[k][2] : S[k][4];
+                g[7] = whi ? Sprev[k][5] : d7;
+                g[8] = whi ? Sprev[k][6] : d8;
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) fout[(int64_t)(k * 9 + i) * pl + oo] = g[k][i];
-                    float hi, lo;
-                    sum9(g[k], hi, lo);
-                    rout[k * pl + oo] = P.rho_ref[k] + (hi + lo);
-                }
+                for (int i = 0; i < 9; ++i) bstore(g[i], fout, off, (uint32_t)(k * 9 + i) * qb);
+                float hi, lo;
+                sum9(g, hi, lo);
+                bstore(hi + lo, rout, roff, (uint32_t)k * qb);
             }
         }
 #pragma unroll
@@ -233,11 +287,19 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
 #pragma unroll
             for (int i = 0; i < 9; ++i) Sprev[k][i] = S[k][i];
         }
-        if (more) {
+        {
+            // the slot of row c - 2 takes row c + 3 (after the last row too,
+            // where it is simply not read)
+            const int freed = slot[0];
+#pragma unroll
+            for (int d = 0; d < RR - 1; ++d) slot[d] = slot[d + 1];
+            slot[RR - 1] = freed;
             __syncthreads();  // every lane has read the ring row about to be replaced
-            ring_store(slot_of(c + 1 + HALO), c + 1 + HALO, vnext);
+            ring_store(freed, rnext, vnext);
             __syncthreads();
+            advance(cr);
         }
+        advance(cc);
     }
 }
 
@@ -320,8 +382,7 @@ __global__ __launch_bounds__(NTHREADS) void k_export(const KInst *__restrict__ i
     const int y = t.z + (int)(threadIdx.x / TX);
     if (x >= P.nx || y >= P.ny) return;
     const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
-    const int64_t o = (int64_t)y * P.pitch + x;
-    for (int j = 0; j < 18; ++j) fout[(int64_t)j * N + n] = P.f[par][(int64_t)j * P.plane + o];
+    for (int j = 0; j < 18; ++j) fout[(int64_t)j * N + n] = P.f[par][fidx(P, j, x, y)];
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_import(const KInst *__restrict__ insts,
@@ -335,8 +396,7 @@ __global__ __launch_bounds__(NTHREADS) void k_import(const KInst *__restrict__ i
     const int y = t.z + (int)(threadIdx.x / TX);
     if (x >= P.nx || y >= P.ny) return;
     const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
-    const int64_t o = (int64_t)y * P.pitch + x;
-    for (int j = 0; j < 18; ++j) P.f[par][(int64_t)j * P.plane + o] = fin[(int64_t)j * N + n];
+    for (int j = 0; j < 18; ++j) P.f[par][fidx(P, j, x, y)] = fin[(int64_t)j * N + n];
 }
 
 // ------------------------------------------------------------------ forces only
@@ -350,7 +410,7 @@ __global__ void k_rho_in(const KInst *__restrict__ insts, int inst, int par, con
         const int k = (int)(n / N);
         const int64_t m = n % N;
         const int y = (int)(m / P.nx), x = (int)(m % P.nx);
-        P.rho[par ^ 1][k * P.plane + (int64_t)y * P.pitch + x] = rho_in[n];
+        P.rho[par ^ 1][ridx(P, k, x, y)] = rho_in[n];
     }
 }
 
@@ -362,7 +422,7 @@ __global__ __launch_bounds__(NTHREADS) void k_forces(const KInst *__restrict__ i
     const int4 t = tiles[blockIdx.x];
     if (t.x != inst) return;  // uniform per block: no thread reaches the barrier below
     const KInst &P = insts[t.x];
-    stage_tile(P, P.rho[par ^ 1], t.y, t.z, T);
+    stage_tile(P, P.rho[par ^ 1], t.y, t.z, T, true);
     __syncthreads();
     const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
     const int x = t.y + lx, y = t.z + ly;
@@ -676,11 +736,23 @@ __global__ __launch_bounds__(RT) void k_red_final3(const KInst *__restrict__ ins
 }
 
 // ------------------------------------------------------------------ copy probe
-__global__ void k_copy(float4 *__restrict__ dst, const float4 *__restrict__ src, int64_t n4)
+// each thread moves CPT 16-byte vectors, all loads issued before the stores
+constexpr int CPT = 4;
+__global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst,
+                                              const float4 *__restrict__ src, int64_t n4)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t base = (int64_t)blockIdx.x * 256 * CPT + threadIdx.x;
+    float4 v[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int64_t i = base + (int64_t)j * 256;
+        if (i < n4) v[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int64_t i = base + (int64_t)j * 256;
+        if (i < n4) dst[i] = v[j];
+    }
 }
 
 __global__ void k_copy_tail(char *__restrict__ dst, const char *__restrict__ src, int64_t n)
@@ -796,7 +868,9 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t 
 {
     const int64_t n4 = (int64_t)(nbytes / 16);
     if (n4 > 0) {
-        k_copy<<<4096, 256, 0, st>>>((float4 *)dst, (const float4 *)src, n4);
+        const int64_t nb = (n4 + 256 * CPT - 1) / (256 * CPT);
+        if (nb > 0x7fffffff) return hipErrorInvalidValue;
+        k_copy<<<(unsigned)nb, 256, 0, st>>>((float4 *)dst, (const float4 *)src, n4);
         LAUNCH_CHECK();
     }
     const int64_t tail = (int64_t)(nbytes - (uint64_t)n4 * 16);

@@ -1,0 +1,64 @@
+"""Strip-height autotuner of the fused step.
+
+Times each candidate strip height with the library's event-timed kernel
+profile (lbm_profile_step), applies the fastest with lbm_set_tiling and caches
+the choice in a JSON file keyed by lattice shapes, instance count and GPU
+architecture.  Any strip height gives bitwise identical results, so tuning
+never changes the simulation.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import lbm
+
+CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 48, 64)
+CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                        "lbm_tiling.json"))
+
+
+def _key(sim, arch: str) -> str:
+    shapes = sorted({(p.nx, p.ny) for p in sim.params})
+    return f"{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
+        (f"|+{len(shapes) - 8}" if len(shapes) > 8 else "")
+
+
+def _arch(sim) -> str:
+    try:
+        return sim.torch.cuda.get_device_properties(sim.device).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True) -> dict:
+    """Pick the fastest strip height for sim's context; returns the timings."""
+    arch = _arch(sim)
+    key = _key(sim, arch)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        try:
+            with open(CACHE) as fh:
+                cache = json.load(fh)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        lbm.lbm_set_tiling(sim.ctx, int(cache[key]["best"]))
+        return cache[key]
+    times = {}
+    for h in candidates:
+        lbm.lbm_set_tiling(sim.ctx, h)
+        lbm.lbm_profile_step(sim.ctx, 3)  # warm-up
+        times[h] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+    best = min(times, key=times.get)
+    lbm.lbm_set_tiling(sim.ctx, best)
+    entry = {"best": best, "ms": {str(k): v for k, v in times.items()}}
+    if use_cache:
+        cache[key] = entry
+        try:
+            os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+            with open(CACHE, "w") as fh:
+                json.dump(cache, fh, indent=1)
+        except OSError:
+            pass
+    return entry
