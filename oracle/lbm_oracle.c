@@ -455,3 +455,345 @@ void ora_fields(const ora_params *p, const double *f, double *rho_out, double *j
     free(rho_arr);
     free(psi);
 }
+
+/* ======================================================================
+ * Reverse-mode adjoint of one time step and differentiable objectives.
+ *
+ * The paper does not treat gradients; this section is the transpose of the
+ * derivative of the step defined above (Eqs. 1, 2, 3, 5, 6, 8, 9 with the
+ * readings listed at the top), written equation by equation in reverse
+ * order.  For one step f(t+1) = Phi(f(t); theta), given
+ * lam_next = dJ/df(t+1) it returns lam = (dPhi/df)^T lam_next and adds
+ * (dPhi/dtheta)^T lam_next to grad, with
+ *   theta = (G1, G2, G_AB, tau_A, tau_B),
+ * where G1 and G2 move the couplings of both components together.
+ * Everything is FP64, no blocking, one node at a time; the nonlocal part of
+ * the force is transposed as a scatter (the literal transpose of the
+ * gather in force_at).
+ * ====================================================================== */
+
+/* Sums of the three stencils of Eqs. 8 and 9 at one node (the bracketed
+ * sums of force_at, without the prefactors). */
+typedef struct {
+    double s1x, s1y; /* sum_i w_i psi_k(x + e_i) e_i over D2Q9   */
+    double s2x, s2y; /* sum_j p_j psi_k(x + e_j) e_j over D2Q25  */
+    double srx, sry; /* sum_i w_i rho_kbar(x + e_i) e_i          */
+} stencil_sums;
+
+static void stencil_sums_at(const ora_params *p, const dens_src *rho, int k, int x, int y,
+                            stencil_sums *s)
+{
+    int kb = 1 - k;
+    memset(s, 0, sizeof(*s));
+    for (int i = 0; i < 9; ++i) {
+        double ps = psi_at(p, rho, k, x + EX[i], y + EY[i]);
+        s->s1x += wi(i) * ps * EX[i];
+        s->s1y += wi(i) * ps * EY[i];
+        double rb = rho_at(p, rho, kb, x + EX[i], y + EY[i]);
+        s->srx += wi(i) * rb * EX[i];
+        s->sry += wi(i) * rb * EY[i];
+    }
+    for (int dy = -2; dy <= 2; ++dy)
+        for (int dx = -2; dx <= 2; ++dx) {
+            double ps = psi_at(p, rho, k, x + dx, y + dy);
+            double pw = p_of(dx * dx + dy * dy);
+            s->s2x += pw * ps * dx;
+            s->s2y += pw * ps * dy;
+        }
+}
+
+/* Lattice node seen at (x, y) with the force stencil's wrapping rules:
+ * returns 0 when (x, y) lies beyond a wall (a fixed virtual density that no
+ * adjoint flows into), else 1 with the wrapped node index in *n. */
+static int node_in_lattice(const ora_params *p, int x, int y, size_t *n)
+{
+    x = wrap(x, p->nx);
+    if (p->walls) {
+        if (y < 0 || y >= p->ny) return 0;
+    } else {
+        y = wrap(y, p->ny);
+    }
+    *n = NODE(p, x, y);
+    return 1;
+}
+
+/* Transpose of the force (Eqs. 8, 9 and F^b = rho g) for a field of force
+ * adjoints Fbar[k][d][y][x]: adds d J / d rho_k to rhobar[k][y][x] (through
+ * psi, the inter-species density and the body force) and the direct coupling
+ * gradients to gG[3] = (G1, G2, G_AB). */
+static void force_transpose(const ora_params *p, const dens_src *rho, const double *Fbar,
+                            double *rhobar, double *gG)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *psibar = (double *)calloc(2 * N, sizeof(double));
+    for (int k = 0; k < 2; ++k) {
+        int kb = 1 - k;
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                size_t n = NODE(p, x, y);
+                double fbx = Fbar[((size_t)k * 2 + 0) * N + n];
+                double fby = Fbar[((size_t)k * 2 + 1) * N + n];
+                if (fbx == 0.0 && fby == 0.0) continue;
+                stencil_sums s;
+                stencil_sums_at(p, rho, k, x, y, &s);
+                double psi_x = psi_at(p, rho, k, x, y);
+                double rho_x = rho_at(p, rho, k, x, y);
+                /* own-node factors: psi_k(x) and rho_k(x) */
+                psibar[(size_t)k * N + n] +=
+                    -p->G1[k] * (s.s1x * fbx + s.s1y * fby) - p->G2[k] * (s.s2x * fbx + s.s2y * fby);
+                rhobar[(size_t)k * N + n] += -p->G_AB * (s.srx * fbx + s.sry * fby)
+                                             + p->g[k][0] * fbx + p->g[k][1] * fby;
+                /* coupling gradients */
+                gG[0] += -psi_x * (s.s1x * fbx + s.s1y * fby);
+                gG[1] += -psi_x * (s.s2x * fbx + s.s2y * fby);
+                gG[2] += -rho_x * (s.srx * fbx + s.sry * fby);
+                /* neighbours: psi_k(x + e) in the two psi stencils */
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        int e2 = dx * dx + dy * dy;
+                        double c = p->G2[k] * p_of(e2) + (e2 <= 2 ? p->G1[k] * w_of(e2) : 0.0);
+                        size_t m;
+                        if (!node_in_lattice(p, x + dx, y + dy, &m)) continue;
+                        psibar[(size_t)k * N + m] += -psi_x * c * (dx * fbx + dy * fby);
+                    }
+                /* neighbours: rho_kbar(x + e_i) in the inter-species stencil */
+                for (int i = 0; i < 9; ++i) {
+                    size_t m;
+                    if (!node_in_lattice(p, x + EX[i], y + EY[i], &m)) continue;
+                    rhobar[(size_t)kb * N + m] +=
+                        -p->G_AB * rho_x * wi(i) * (EX[i] * fbx + EY[i] * fby);
+                }
+            }
+    }
+    /* psi_k = rho0 (1 - exp(-rho_k / rho0))  =>  dpsi/drho = exp(-rho_k / rho0) */
+    for (int k = 0; k < 2; ++k)
+        for (size_t n = 0; n < N; ++n)
+            rhobar[(size_t)k * N + n] +=
+                psibar[(size_t)k * N + n] * exp(-rho->rho[(size_t)k * N + n] / p->rho0);
+    free(psibar);
+}
+
+/* Adjoint of one step.  f = state at t, lam_next = dJ/df(t+1), both
+ * [k][i][y][x]; writes lam = dJ/df(t) and adds to grad[5].
+ * work must hold 10*nx*ny doubles. */
+void ora_adjoint_step(const ora_params *p, const double *f, const double *lam_next, double *lam,
+                      double *grad, double *work)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *rho_arr = work, *psi = work + 2 * N, *Fbar = work + 4 * N, *rhobar = work + 8 * N;
+    ora_density(p, f, rho_arr);
+    psi_field(p, rho_arr, psi);
+    dens_src rho = {rho_arr, psi, NULL};
+    memset(Fbar, 0, 4 * N * sizeof(double));
+    memset(rhobar, 0, 2 * N * sizeof(double));
+    double gtau[2] = {0.0, 0.0};
+
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t n = NODE(p, x, y);
+            node_macro m;
+            macro_at(p, f, &rho, x, y, &m);
+            double D = m.rho[0] / p->tau[0] + m.rho[1] / p->tau[1];
+            double uu = m.ux * m.ux + m.uy * m.uy;
+
+            /* transpose of streaming: the post-collision f*_{k,i}(x) went to
+             * x + e_i, or back to x reversed across a wall */
+            double a[2][9];
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 9; ++i) {
+                    int yd = y + EY[i];
+                    if (p->walls && (yd < 0 || yd >= p->ny))
+                        a[k][i] = lam_next[FIDX(p, k, OPP[i], x, y)];
+                    else
+                        a[k][i] = lam_next[FIDX(p, k, i, wrap(x + EX[i], p->nx), wrap(yd, p->ny))];
+                }
+
+            /* transpose of Eq. 1 (BGK + Guo) at fixed rho_k, u, F_k */
+            double ubx = 0.0, uby = 0.0;
+            double rbar[2], Fbx[2], Fby[2];
+            for (int k = 0; k < 2; ++k) {
+                double tau = p->tau[k], c = 1.0 - 1.0 / (2.0 * tau);
+                rbar[k] = 0.0;
+                Fbx[k] = 0.0;
+                Fby[k] = 0.0;
+                for (int i = 0; i < 9; ++i) {
+                    double eu = EX[i] * m.ux + EY[i] * m.uy;
+                    double eF = EX[i] * m.Fx[k] + EY[i] * m.Fy[k];
+                    double E = 1.0 + eu / CS2 + (eu * eu - CS2 * uu) / (2.0 * CS2 * CS2);
+                    /* f^eq = w rho E(u) */
+                    rbar[k] += a[k][i] * wi(i) * E / tau;
+                    double dEx = EX[i] / CS2 + eu * EX[i] / (CS2 * CS2) - m.ux / CS2;
+                    double dEy = EY[i] / CS2 + eu * EY[i] / (CS2 * CS2) - m.uy / CS2;
+                    ubx += a[k][i] / tau * wi(i) * m.rho[k] * dEx;
+                    uby += a[k][i] / tau * wi(i) * m.rho[k] * dEy;
+                    /* Guo term c w [ (e - u)/cs2 + (e.u) e / cs4 ] . F */
+                    double gx = (EX[i] - m.ux) / CS2 + eu * EX[i] / (CS2 * CS2);
+                    double gy = (EY[i] - m.uy) / CS2 + eu * EY[i] / (CS2 * CS2);
+                    Fbx[k] += a[k][i] * c * wi(i) * gx;
+                    Fby[k] += a[k][i] * c * wi(i) * gy;
+                    ubx += a[k][i] * c * wi(i) * (-m.Fx[k] / CS2 + eF * EX[i] / (CS2 * CS2));
+                    uby += a[k][i] * c * wi(i) * (-m.Fy[k] / CS2 + eF * EY[i] / (CS2 * CS2));
+                    /* tau_k: -(f - feq)/tau and the (1 - 1/(2 tau)) factor */
+                    double fi = f[FIDX(p, k, i, x, y)];
+                    double eq = wi(i) * m.rho[k] * E;
+                    gtau[k] += a[k][i] * (fi - eq) / (tau * tau);
+                    gtau[k] += a[k][i] * wi(i) * (gx * m.Fx[k] + gy * m.Fy[k]) / (2.0 * tau * tau);
+                }
+            }
+            /* transpose of Eq. 3: u = sum_k j_k/tau_k / D, D = sum_k rho_k/tau_k */
+            double mbx[2], mby[2];
+            for (int k = 0; k < 2; ++k) {
+                double tau = p->tau[k];
+                double jbx = ubx / (tau * D), jby = uby / (tau * D);
+                rbar[k] += -(ubx * m.ux + uby * m.uy) / (tau * D);
+                gtau[k] += (ubx * (m.ux * m.rho[k] - m.jx[k]) + uby * (m.uy * m.rho[k] - m.jy[k]))
+                           / (tau * tau * D);
+                /* Eq. 6: j = sum f e + F/2 */
+                mbx[k] = jbx;
+                mby[k] = jby;
+                Fbx[k] += 0.5 * jbx;
+                Fby[k] += 0.5 * jby;
+            }
+            for (int k = 0; k < 2; ++k) {
+                double tau = p->tau[k];
+                for (int i = 0; i < 9; ++i)
+                    lam[FIDX(p, k, i, x, y)] =
+                        (1.0 - 1.0 / tau) * a[k][i] + mbx[k] * EX[i] + mby[k] * EY[i];
+                rhobar[(size_t)k * N + n] += rbar[k];
+                Fbar[((size_t)k * 2 + 0) * N + n] = Fbx[k];
+                Fbar[((size_t)k * 2 + 1) * N + n] = Fby[k];
+            }
+        }
+
+    /* transpose of the forces, then of Eq. 6's density sum */
+    double gG[3] = {0.0, 0.0, 0.0};
+    force_transpose(p, &rho, Fbar, rhobar, gG);
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i)
+            for (size_t n = 0; n < N; ++n) lam[((size_t)k * 9 + i) * N + n] += rhobar[(size_t)k * N + n];
+    grad[0] += gG[0];
+    grad[1] += gG[1];
+    grad[2] += gG[2];
+    grad[3] += gtau[0];
+    grad[4] += gtau[1];
+}
+
+/* Differentiable objectives of a state f (not in the paper; built on its
+ * observables).  Returns J; if lam is not NULL writes dJ/df [k][i][y][x];
+ * if dtheta is not NULL adds the direct dJ/dtheta (theta as above).
+ *   0  J_dp   smooth pressure jump <p_b>_A - <p_b>_B, p_b of Eq. 11,
+ *             weights chi_A = max(0, phi)^4, chi_B = max(0, -phi)^4,
+ *             phi = (rho_A - rho_B) / (rho_A + rho_B)  (bulk phases count,
+ *             interfaces do not; tolerates drifting droplets)
+ *   1  J_Q    flow rate Q = sum_y ubar(y) = (1/nx) sum_x u_x, u barycentric
+ *             with F/2 (Eq. 7); the relative effective viscosity of
+ *             Sec. III D is Q_0 / Q
+ *   2  J_momA x-momentum of the populations of A, sum_{x,i} f_{A,i} e_{i,x}
+ *   3  J_mom  total x-momentum of the populations (its theta-gradient is
+ *             exactly zero: the interaction forces sum to zero)
+ *   4  J_massA mass of A (theta-gradient exactly zero)
+ * work must hold 10*nx*ny doubles. */
+double ora_objective(const ora_params *p, const double *f, int which, double *lam, double *dtheta,
+                     double *work)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *rho_arr = work, *psi = work + 2 * N, *Fbar = work + 4 * N, *rhobar = work + 8 * N;
+    ora_density(p, f, rho_arr);
+    psi_field(p, rho_arr, psi);
+    dens_src rho = {rho_arr, psi, NULL};
+    memset(Fbar, 0, 4 * N * sizeof(double));
+    memset(rhobar, 0, 2 * N * sizeof(double));
+    if (lam) memset(lam, 0, 18 * N * sizeof(double));
+    double J = 0.0;
+
+    if (which == 0) {
+        double SA = 0.0, SB = 0.0, PA = 0.0, PB = 0.0;
+        double dPA[3] = {0, 0, 0}, dPB[3] = {0, 0, 0};
+        for (size_t n = 0; n < N; ++n) {
+            double ra = rho_arr[n], rb = rho_arr[N + n];
+            double pa = psi[n], pb_ = psi[N + n];
+            double pr = CS2 * (ra + 0.5 * (p->G1[0] + p->G2[0]) * pa * pa + rb
+                               + 0.5 * (p->G1[1] + p->G2[1]) * pb_ * pb_ + p->G_AB * ra * rb);
+            double phi = (ra - rb) / (ra + rb);
+            double ca = phi > 0 ? phi * phi * phi * phi : 0.0;
+            double cb = phi < 0 ? phi * phi * phi * phi : 0.0;
+            double dG12 = CS2 * 0.5 * (pa * pa + pb_ * pb_), dGab = CS2 * ra * rb;
+            SA += ca;
+            SB += cb;
+            PA += pr * ca;
+            PB += pr * cb;
+            dPA[0] += dG12 * ca; dPA[1] += dG12 * ca; dPA[2] += dGab * ca;
+            dPB[0] += dG12 * cb; dPB[1] += dG12 * cb; dPB[2] += dGab * cb;
+        }
+        double mA = PA / SA, mB = PB / SB;
+        J = mA - mB;
+        if (dtheta)
+            for (int t = 0; t < 3; ++t) dtheta[t] += dPA[t] / SA - dPB[t] / SB;
+        if (lam)
+            for (size_t n = 0; n < N; ++n) {
+                double ra = rho_arr[n], rb = rho_arr[N + n];
+                double pa = psi[n], pb_ = psi[N + n];
+                double pr = CS2 * (ra + 0.5 * (p->G1[0] + p->G2[0]) * pa * pa + rb
+                                   + 0.5 * (p->G1[1] + p->G2[1]) * pb_ * pb_ + p->G_AB * ra * rb);
+                double s = ra + rb, phi = (ra - rb) / s;
+                double dphi[2] = {2.0 * rb / (s * s), -2.0 * ra / (s * s)};
+                double dp[2] = {
+                    CS2 * (1.0 + (p->G1[0] + p->G2[0]) * pa * exp(-ra / p->rho0) + p->G_AB * rb),
+                    CS2 * (1.0 + (p->G1[1] + p->G2[1]) * pb_ * exp(-rb / p->rho0) + p->G_AB * ra)};
+                double ca = phi > 0 ? phi * phi * phi * phi : 0.0;
+                double cb = phi < 0 ? phi * phi * phi * phi : 0.0;
+                double dca = phi > 0 ? 4.0 * phi * phi * phi : 0.0;
+                double dcb = phi < 0 ? 4.0 * phi * phi * phi : 0.0;
+                for (int k = 0; k < 2; ++k) {
+                    double d = (dp[k] * ca + (pr - mA) * dca * dphi[k]) / SA
+                               - (dp[k] * cb + (pr - mB) * dcb * dphi[k]) / SB;
+                    for (int i = 0; i < 9; ++i) lam[((size_t)k * 9 + i) * N + n] = d;
+                }
+            }
+        return J;
+    }
+
+    if (which == 1) {
+        double inv_nx = 1.0 / p->nx;
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                size_t n = NODE(p, x, y);
+                node_macro m;
+                macro_at(p, f, &rho, x, y, &m);
+                double rt = m.rho[0] + m.rho[1];
+                double ux = (m.jx[0] + m.jx[1]) / rt;
+                J += ux * inv_nx;
+                for (int k = 0; k < 2; ++k) {
+                    /* u_x = (sum_k m_kx + F_kx / 2) / rho */
+                    if (lam)
+                        for (int i = 0; i < 9; ++i)
+                            lam[FIDX(p, k, i, x, y)] = inv_nx * (EX[i] - ux) / rt;
+                    Fbar[((size_t)k * 2 + 0) * N + n] = 0.5 * inv_nx / rt;
+                }
+            }
+        double gG[3] = {0.0, 0.0, 0.0};
+        force_transpose(p, &rho, Fbar, rhobar, gG);
+        if (lam)
+            for (int k = 0; k < 2; ++k)
+                for (int i = 0; i < 9; ++i)
+                    for (size_t n = 0; n < N; ++n)
+                        lam[((size_t)k * 9 + i) * N + n] += rhobar[(size_t)k * N + n];
+        if (dtheta)
+            for (int t = 0; t < 3; ++t) dtheta[t] += gG[t];
+        return J;
+    }
+
+    /* linear functionals of the populations */
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i) {
+            double c;
+            if (which == 2) c = k == 0 ? EX[i] : 0.0;
+            else if (which == 3) c = EX[i];
+            else c = k == 0 ? 1.0 : 0.0;
+            for (size_t n = 0; n < N; ++n) {
+                J += c * f[((size_t)k * 9 + i) * N + n];
+                if (lam) lam[((size_t)k * 9 + i) * N + n] = c;
+            }
+        }
+    return J;
+}

@@ -89,9 +89,9 @@ def lib():
         L.ora_init.argtypes = [P, _D, _D, _D]
         L.ora_fields.argtypes = [P, _D, _D, _D, _D, _D, _D, _D]
         L.ora_threads.restype = ctypes.c_int
-        if hasattr(L, "ora_adjoint_step"):
-            L.ora_adjoint_step.argtypes = [P, _D, _D, _D, _D]
-            L.ora_objective.argtypes = [P, ctypes.c_int, _D, _D, _D, _D]
+        L.ora_adjoint_step.argtypes = [P, _D, _D, _D, _D, _D]
+        L.ora_objective.argtypes = [P, _D, ctypes.c_int, _D, _D, _D]
+        L.ora_objective.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -196,6 +196,70 @@ def fields(p: Params, f: np.ndarray) -> dict:
     lib().ora_fields(ctypes.byref(c), _ptr(f), _ptr(out["rho"]), _ptr(out["j"]),
                      _ptr(out["F"]), _ptr(out["ueq"]), _ptr(out["u"]), _ptr(out["pb"]))
     return out
+
+
+# ---------------------------------------------------------------- adjoint (FP64)
+THETA_NAMES = ("G1", "G2", "G_AB", "tau_A", "tau_B")
+OBJECTIVES = {"dp": 0, "Q": 1, "momA": 2, "mom": 3, "massA": 4}
+
+
+def with_theta(p: Params, theta) -> Params:
+    """p with theta = (G1, G2, G_AB, tau_A, tau_B); G1, G2 set for both components."""
+    t = [float(v) for v in theta]
+    return dataclasses.replace(p, G1=(t[0], t[0]), G2=(t[1], t[1]), G_AB=t[2], tau=(t[3], t[4]))
+
+
+def theta_of(p: Params) -> np.ndarray:
+    def first(v):
+        return float(v) if np.isscalar(v) else float(v[0])
+    return np.array([first(p.G1), first(p.G2), float(p.G_AB), float(p.tau[0]), float(p.tau[1])])
+
+
+def adjoint_step(p: Params, f: np.ndarray, lam_next: np.ndarray):
+    """(dPhi/df)^T lam_next and (dPhi/dtheta)^T lam_next for one step from state f."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lam_next = np.ascontiguousarray(lam_next, dtype=np.float64)
+    lam = np.zeros_like(f)
+    grad = np.zeros(5)
+    work = np.zeros((10, p.ny, p.nx))
+    c = p.c()
+    lib().ora_adjoint_step(ctypes.byref(c), _ptr(f), _ptr(lam_next), _ptr(lam), _ptr(grad),
+                           _ptr(work))
+    return lam, grad
+
+
+def objective(p: Params, f: np.ndarray, which: str | int):
+    """(J, dJ/df, direct dJ/dtheta) of a differentiable observable of state f."""
+    w = OBJECTIVES[which] if isinstance(which, str) else int(which)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    lam = np.zeros_like(f)
+    dth = np.zeros(5)
+    work = np.zeros((10, p.ny, p.nx))
+    c = p.c()
+    J = lib().ora_objective(ctypes.byref(c), _ptr(f), w, _ptr(lam), _ptr(dth), _ptr(work))
+    return float(J), lam, dth
+
+
+def value_and_grad(p: Params, f0: np.ndarray, steps: int, which: str | int):
+    """J(f(steps)) and its gradients with respect to theta and f0.
+
+    Stores every intermediate state (small lattices only) and runs the
+    adjoint steps backwards from the objective's seed.
+    """
+    states = [np.ascontiguousarray(f0, dtype=np.float64)]
+    for _ in range(steps):
+        states.append(step(p, states[-1]))
+    J, lam, g = objective(p, states[-1], which)
+    g = g.copy()
+    for t in range(steps - 1, -1, -1):
+        lam, gs = adjoint_step(p, states[t], lam)
+        g += gs
+    return J, g, lam
+
+
+def objective_after(p: Params, f0: np.ndarray, steps: int, which: str | int) -> float:
+    """J(f(steps)) only (for finite differences)."""
+    return objective(p, run(p, f0, steps), which)[0]
 
 
 # ---------------------------------------------------------------- observables (numpy, FP64)
