@@ -19,7 +19,8 @@
  *
  * Arithmetic is FP32; populations are stored as FP32 deviations
  * f_{k,i} - w_i rho_ref[k].  FP64 is used on the device only in the
- * reductions behind lbm_observables and the parameter gradients.
+ * reductions behind lbm_observables, lbm_adjoint_seed and the parameter
+ * gradients of lbm_adjoint_step.
  *
  * Memory ownership: the caller allocates ONE device workspace of
  * lbm_workspace_bytes() bytes and every device buffer passed to an entry
@@ -158,6 +159,75 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
  * stream and discards captured graphs. */
 int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows);
 int32_t lbm_get_tiling(const lbm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Reverse-mode adjoint (gradients of objectives with respect to the state and
+ * to theta = (G1, G2, G_AB, tau_A, tau_B), where G1 and G2 move the couplings
+ * of Eq. 8 of both components together).  The paper has no adjoint; these
+ * entry points differentiate the step defined by Eqs. 1, 2, 3, 5, 6, 8, 9
+ * exactly as lbm_step computes it (same readings).  State and adjoint
+ * buffers are the caller's, device FP32, in the lbm_get_populations layout
+ * [2][9][ny][nx]; state buffers hold deviations as lbm_get_populations
+ * writes them.  The adjoint kernels use the instance's field scratch (what
+ * lbm_fields last left there is overwritten).
+ * ------------------------------------------------------------------------ */
+
+/* Objectives of lbm_adjoint_seed (built on the paper's observables). */
+#define LBM_OBJ_DP 0      /* smooth pressure jump <p_b>_A - <p_b>_B, p_b of Eq. 11 averaged
+                             with weights max(0, +-phi)^4, phi = (rho_A - rho_B)/(rho_A + rho_B)
+                             (Laplace test of Sec. III B without a droplet centre)            */
+#define LBM_OBJ_Q 1       /* flow rate Q = (1/nx) sum_x u_x, u barycentric (Eq. 7); the
+                             relative effective viscosity of Sec. III D is Q_0 / Q           */
+#define LBM_OBJ_MOM_A 2   /* x-momentum of the populations of A, sum f_{A,i} e_{i,x}          */
+#define LBM_OBJ_MOM 3     /* total x-momentum of the populations (theta-gradient zero)      */
+#define LBM_OBJ_MASS_A 4  /* mass of A (theta-gradient zero)                                */
+
+/* Adjoint of one time step of instance inst taken from state f_dev (time t):
+ * lam_out_dev = (d f(t+1) / d f(t))^T lam_in_dev, and
+ * grad_dev[0..4] += (d f(t+1) / d theta)^T lam_in_dev (device FP64, may be
+ * NULL to skip the gradient).  lam_out_dev must not overlap f_dev or
+ * lam_in_dev.  Asynchronous on the context's stream; consecutive calls on
+ * one context are ordered by the stream. */
+int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
+                     float *lam_out_dev, double *grad_dev);
+
+/* Forward run that keeps its states, for checkpoint-recompute: for
+ * j = 0..nsteps-1, writes the populations of instance inst (lbm_get_populations
+ * layout) into f_store_dev + j*18*nx*ny, then advances the context by one
+ * step (every instance).  f_store_dev holds nsteps states.  Asynchronous. */
+int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev);
+
+/* nsteps adjoint steps back through a recorded window: on entry lam_dev holds
+ * dJ/df(t0 + nsteps), on return dJ/df(t0); f_store_dev holds the states
+ * f(t0 + j), j = 0..nsteps-1 (as lbm_record writes them).  tmp_dev is a
+ * buffer of one state's size; neither may overlap the store or each other.
+ * grad_dev[0..4] (device FP64, may be NULL) += the theta-gradient of the
+ * window, reduced once in a fixed order.  Asynchronous. */
+int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_store_dev,
+                    float *lam_dev, float *tmp_dev, double *grad_dev);
+
+/* Objective J(f) of state f_dev of instance inst (one of LBM_OBJ_*): *J
+ * receives its value (FP64 accumulation), dtheta[0..4] the direct partial
+ * derivatives dJ/dtheta at fixed f (host), and lam_dev (device, may be NULL
+ * except for LBM_OBJ_Q) the seed dJ/df.  Synchronises the stream.  Returns
+ * LBM_EINVAL if the pressure-jump objective finds only one phase. */
+int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, int32_t objective, const float *f_dev,
+                     float *lam_dev, double *J, double *dtheta);
+
+/* Replace the model parameters of instance inst (couplings, relaxation
+ * times, body force, pseudopotential scale, wall densities); nx, ny, walls
+ * and rho_ref must equal the current ones (LBM_EINVAL otherwise), so the
+ * state stays valid.  Synchronises the stream; captured graphs stay valid
+ * and use the new values. */
+int lbm_set_params(lbm_ctx *ctx, int32_t inst, const lbm_params *params);
+
+/* Time the kernels of one adjoint step of instance inst like
+ * lbm_profile_step (nrep launches of each kernel between HIP events on the
+ * context's stream).  lam_out_dev and grad_dev are overwritten with
+ * meaningless values.  Synchronises the stream. */
+int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
+                        float *lam_out_dev, double *grad_dev, int32_t nrep, int32_t max_k,
+                        double *ms, const char **names, int32_t *n_kernels);
 
 /* Release host resources of the context (graphs, metadata).  Synchronises
  * the stream; never frees caller memory. */

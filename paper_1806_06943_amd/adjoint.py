@@ -1,0 +1,138 @@
+"""Gradients of LBM objectives with respect to the model parameters.
+
+theta = (G1, G2, G_AB, tau_A, tau_B): the couplings of Eqs. 8 and 9 (G1 and
+G2 move both components together) and the relaxation times of Eq. 1
+(arXiv:1806.06943).  An objective J (pressure jump, flow rate, momentum,
+mass; see ``lbm.OBJECTIVES``) of the state after a number of steps is
+differentiated in reverse mode with checkpoint-and-recompute: the forward
+pass keeps the state at the start of each window of steps; the backward pass
+re-runs each window forward from its checkpoint, storing its states, and
+applies the library's adjoint step (``lbm_adjoint_step``) backwards through
+the window.  Memory: one state per window boundary plus ``window`` states.
+
+Argument marshalling and bookkeeping only: the step, the adjoint step and the
+objective seeds all run in the HIP library.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import lbm
+
+
+class Problem:
+    """J(f(steps); theta) for one lattice instance, with its gradient.
+
+    ``instance`` is an instance dict for ``lbm.Sim``; the initial state is the
+    equilibrium at rest of its densities (as ``lbm_init`` builds it).
+    """
+
+    def __init__(self, instance: dict, steps: int, objective: str, window: int = 200,
+                 device: str = "cuda:0"):
+        if steps < 0 or window < 1:
+            raise ValueError("steps must be >= 0 and window >= 1")
+        self.sim = lbm.Sim([instance], device=device)
+        self.torch = self.sim.torch
+        self.steps = int(steps)
+        self.window = int(window)
+        self.objective = objective
+        self.f0 = self.sim.populations(0).clone()
+        p = self.sim.params[0]
+        self.shape = (2, 9, p.ny, p.nx)
+        self.nodes = p.nx * p.ny
+        self._store = None
+
+    def theta(self) -> np.ndarray:
+        return self.sim.theta(0)
+
+    def _windows(self):
+        out, s = [], 0
+        while s < self.steps:
+            n = min(self.window, self.steps - s)
+            out.append((s, n))
+            s += n
+        return out
+
+    def forward(self, theta):
+        """J at theta; returns (J, saved) where saved feeds ``backward``."""
+        t = self.torch
+        self.sim.set_theta(theta)
+        self.sim.set_populations(self.f0)
+        ckpts = []
+        for _, n in self._windows():
+            c = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
+            self.sim.populations_into(c)
+            ckpts.append(c)
+            self.sim.step(n)
+        fT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
+        self.sim.populations_into(fT)
+        lamT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
+        J, direct = self.sim.adjoint_seed(self.objective, fT, lamT)
+        return J, (np.asarray(theta, dtype=np.float64).copy(), ckpts, lamT, direct)
+
+    def backward(self, saved):
+        """(dJ/dtheta as numpy float64[5], dJ/df(0) as a device tensor)."""
+        t = self.torch
+        theta, ckpts, lamT, direct = saved
+        self.sim.set_theta(theta)
+        if self._store is None or self._store.shape[0] < min(self.window, max(self.steps, 1)):
+            self._store = t.empty((min(self.window, max(self.steps, 1)),) + self.shape,
+                                  dtype=t.float32, device=self.sim.device)
+        S = self._store
+        grad = t.zeros(5, dtype=t.float64, device=self.sim.device)
+        lam = lamT.clone()
+        tmp = t.empty_like(lam)
+        wins = self._windows()
+        ctx = self.sim.ctx
+        for w in range(len(wins) - 1, -1, -1):
+            _, n = wins[w]
+            # re-run the window from its checkpoint, keeping the state before each
+            # step, then the adjoint steps back through it (two library calls)
+            self.sim.set_populations(ckpts[w])
+            lbm.lbm_record(ctx, 0, n, S.data_ptr())
+            lbm.lbm_adjoint_run(ctx, 0, n, S.data_ptr(), lam.data_ptr(), tmp.data_ptr(),
+                                grad.data_ptr())
+        g = grad.cpu().numpy() + direct
+        return g, lam
+
+    def value_and_grad(self, theta=None):
+        theta = self.theta() if theta is None else theta
+        J, saved = self.forward(theta)
+        g, lam0 = self.backward(saved)
+        return J, g, lam0
+
+    def close(self):
+        self.sim.close()
+
+
+def _function():
+    import torch
+
+    class LBMObjective(torch.autograd.Function):
+        """J(theta) of a Problem as a differentiable torch scalar (float64, CPU)."""
+
+        @staticmethod
+        def forward(ctx, theta, problem):
+            J, saved = problem.forward(theta.detach().cpu().double().numpy())
+            ctx.problem = problem
+            ctx.saved = saved
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g, _ = ctx.problem.backward(ctx.saved)
+            ctx.saved = None
+            return gJ * torch.from_numpy(g), None
+
+    return LBMObjective
+
+
+_FN = None
+
+
+def objective(theta, problem: Problem):
+    """Differentiable J(theta): ``theta`` a float64 tensor of 5 values."""
+    global _FN
+    if _FN is None:
+        _FN = _function()
+    return _FN.apply(theta, problem)

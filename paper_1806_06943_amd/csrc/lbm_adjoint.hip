@@ -1,0 +1,629 @@
+// Reverse-mode adjoint of the two-range pseudopotential LBM step and the
+// seeds of differentiable objectives, for gfx950.
+//
+// The step (arXiv:1806.06943, Eqs. 1, 2, 3, 5, 6, 8, 9; Sec. II B) maps the
+// populations f(t) to f(t+1) = Phi(f(t); theta).  Given lam_next = dJ/df(t+1)
+// the adjoint step returns lam = (dPhi/df)^T lam_next and adds
+// (dPhi/dtheta)^T lam_next to a gradient, theta = (G1, G2, G_AB, tau_A,
+// tau_B) with G1 and G2 moving both components together.
+//
+// Buffers are the caller's, in the population export layout [2][9][ny][nx]
+// (FP32 deviations f - w_i rho_ref for the state; plain FP32 for lam).  One
+// adjoint step is three passes over 64 x 4 tiles:
+//   k_adj_density  density deviations of f (TwoSum, as the forward step)
+//                  into scratch plane pair rdev;
+//   k_adj_local    per node: recompute rho, psi, the stencil sums of Eqs. 8
+//                  and 9 (LDS tile with a halo of 2), F, j, u^eq; gather
+//                  lam*_{k,i}(x) = lam_next_{k,i}(x + e_i) (transpose of
+//                  streaming, reversed across a wall); transpose the
+//                  collision, Eq. 3 and Eq. 6; write the force adjoint Fbar
+//                  and the partial lam (everything but the force stencil's
+//                  neighbour terms); accumulate the theta terms in FP64;
+//   k_adj_force    per node: gather the neighbour terms of the transposed
+//                  force stencils from psi Fbar and rho Fbar of the 5 x 5
+//                  neighbourhood (LDS tile) and add the density adjoint to
+//                  all nine directions of lam;
+// followed by a fixed-order FP64 reduction of the per-block theta partials.
+// Scratch (densities, Fbar, block partials) lives in the instance's field
+// planes of the workspace.
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int AW = TX + 2 * HALO;  // staged tile width
+constexpr int AH = TY + 2 * HALO;  // staged tile height
+
+__device__ __forceinline__ int64_t xidx(const AdjPar &A, int q, int x, int y)
+{
+    return ((int64_t)q * A.ny + y) * A.nx + x;  // export layout [q][y][x]
+}
+
+__device__ __forceinline__ int64_t sidx(const AdjPar &A, int plane, int x, int y)
+{
+    return (int64_t)plane * A.plane + (int64_t)y * A.pitch + x;  // scratch planes
+}
+
+__device__ __forceinline__ float apsi(const AdjPar &A, float r)
+{
+    return -A.rho0 * expm1f(-r * A.inv_rho0);
+}
+
+// D2Q9 (order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
+// 7:(-1,-1) 8:(1,-1)) with weights c_i / 36
+__constant__ int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int c_op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
+__device__ __forceinline__ float wgt(int i) { return i == 0 ? W0 : (i < 5 ? W1 : W2); }
+constexpr double wgt9[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// D2Q25 weights p(|e|^2) of Eq. 8 for |e|^2 = 1, 2, 4, 5, 8
+constexpr float P1 = 4.0f / 63.0f, P2 = 4.0f / 135.0f, P4 = 1.0f / 180.0f, P5 = 2.0f / 945.0f,
+                P8 = 1.0f / 15120.0f;
+constexpr double DW1 = 1.0 / 9.0, DW2 = 1.0 / 36.0;
+constexpr double DP1 = 4.0 / 63.0, DP2 = 4.0 / 135.0, DP4 = 1.0 / 180.0, DP5 = 2.0 / 945.0,
+                 DP8 = 1.0 / 15120.0;
+
+// Stencil sum sum_e c(|e|^2) v(x + e) e over the 24 non-zero D2Q25 vectors,
+// as antisymmetric pairs v(x+e) - v(x-e); v(dx, dy) reads the staged tile.
+// T is the accumulation type: FP64 sums of FP32 tile values are exact in
+// the pair differences and keep the relative accuracy of a result much
+// smaller than its terms (interfaces), which the parameter gradients need.
+template <class T, class V>
+__device__ __forceinline__ void sum25(const V &v, T c1, T c2, T c4, T c5, T c8, T &sx, T &sy)
+{
+    auto d = [&](int ax, int ay, int bx, int by) { return (T)v(ax, ay) - (T)v(bx, by); };
+    const T d10 = d(1, 0, -1, 0), d01 = d(0, 1, 0, -1);
+    const T d20 = d(2, 0, -2, 0), d02 = d(0, 2, 0, -2);
+    const T d11 = d(1, 1, -1, -1), dm11 = d(-1, 1, 1, -1);
+    const T d21 = d(2, 1, -2, -1), dm21 = d(-2, 1, 2, -1);
+    const T d12 = d(1, 2, -1, -2), dm12 = d(-1, 2, 1, -2);
+    const T d22 = d(2, 2, -2, -2), dm22 = d(-2, 2, 2, -2);
+    sx = c1 * d10 + (T)2 * c4 * d20 + c2 * (d11 - dm11) + c5 * ((T)2 * (d21 - dm21) + (d12 - dm12)) +
+         (T)2 * c8 * (d22 - dm22);
+    sy = c1 * d01 + (T)2 * c4 * d02 + c2 * (d11 + dm11) + c5 * ((d21 + dm21) + (T)2 * (d12 + dm12)) +
+         (T)2 * c8 * (d22 + dm22);
+}
+
+// the D2Q9 part only (|e|^2 = 1, 2)
+template <class T, class V>
+__device__ __forceinline__ void sum9s(const V &v, T c1, T c2, T &sx, T &sy)
+{
+    auto d = [&](int ax, int ay, int bx, int by) { return (T)v(ax, ay) - (T)v(bx, by); };
+    const T d10 = d(1, 0, -1, 0), d01 = d(0, 1, 0, -1);
+    const T d11 = d(1, 1, -1, -1), dm11 = d(-1, 1, 1, -1);
+    sx = c1 * d10 + c2 * (d11 - dm11);
+    sy = c1 * d01 + c2 * (d11 + dm11);
+}
+
+// Sum of NV doubles over the block (256 threads = 4 wavefronts) in a fixed
+// order; thread 0 writes out[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out, bool accumulate = false)
+{
+    __shared__ double red[NTHREADS / 64][NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = v[j];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        v[j] = s;
+    }
+    const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+    if (ln == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) red[wv][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < NTHREADS / 64; ++w) s += red[w][j];
+            out[j] = accumulate ? out[j] + s : s;
+        }
+}
+
+__device__ __forceinline__ int block_id() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// ---------------------------------------------------------------- densities
+__global__ __launch_bounds__(NTHREADS) void k_adj_density(AdjPar A, const float *__restrict__ f)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    if (x >= A.nx || y >= A.ny) return;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        float v[9], hi, lo;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = f[xidx(A, k * 9 + i, x, y)];
+        sum9(v, hi, lo);
+        A.scr[sidx(A, SCR_RDEV + k, x, y)] = hi + lo;
+    }
+}
+
+// Stage rho and psi of both components over the tile and its halo of 2
+// (periodic in x, periodic in y or the wall densities beyond a wall).
+struct RTile {
+    float rho[2][AH][AW];
+    float psi[2][AH][AW];
+};
+
+__device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile &T)
+{
+    for (int t = threadIdx.x; t < AW * AH; t += NTHREADS) {
+        const int lx = t % AW, ly = t / AW;
+        const int gx = wrapi(x0 + lx - HALO, A.nx);
+        int gy = y0 + ly - HALO;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            float r, p;
+            if (A.walls && (gy < 0 || gy >= A.ny)) {
+                r = A.rho_wall[k];
+                p = A.psi_wall[k];
+            } else {
+                const int yy = wrapi(gy, A.ny);
+                r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, gx, yy)];
+                p = apsi(A, r);
+            }
+            T.rho[k][ly][lx] = r;
+            T.psi[k][ly][lx] = p;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- local transpose
+// MODE 0: adjoint step.  MODE 1: seed of J_Q = (1/nx) sum_x u_x.
+// Block partials: [0..4] theta, [5] J.
+template <int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *__restrict__ f,
+                                                        const float *__restrict__ lam_next,
+                                                        float *__restrict__ lam)
+{
+    __shared__ RTile T;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    stage_rho(A, x0, y0, T);
+    __syncthreads();
+    const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
+    const int x = x0 + lx, y = y0 + ly;
+    double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < A.nx && y < A.ny) {
+        const int cx = lx + HALO, cy = ly + HALO;
+        float rho[2], psi[2], drho[2], mx[2], my[2], F[2][2];
+        double s1[2][2], s2[2][2], sr[2][2];
+        float dev[2][9];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dev[k][i] = f[xidx(A, k * 9 + i, x, y)];
+            rho[k] = T.rho[k][cy][cx];
+            psi[k] = T.psi[k][cy][cx];
+            drho[k] = A.scr[sidx(A, SCR_RDEV + k, x, y)];
+            mx[k] = (dev[k][1] - dev[k][3]) + (dev[k][5] - dev[k][7]) + (dev[k][8] - dev[k][6]);
+            my[k] = (dev[k][2] - dev[k][4]) + (dev[k][5] - dev[k][7]) + (dev[k][6] - dev[k][8]);
+            auto vp = [&](int dx, int dy) { return T.psi[k][cy + dy][cx + dx]; };
+            auto vr = [&](int dx, int dy) { return T.rho[1 - k][cy + dy][cx + dx]; };
+            sum9s<double>(vp, DW1, DW2, s1[k][0], s1[k][1]);
+            sum25<double>(vp, DP1, DP2, DP4, DP5, DP8, s2[k][0], s2[k][1]);
+            sum9s<double>(vr, DW1, DW2, sr[k][0], sr[k][1]);
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+                F[k][d] = (float)(-(double)psi[k] * ((double)A.G1[k] * s1[k][d] + (double)A.G2[k] * s2[k][d]) -
+                                  (double)A.gab * (double)rho[k] * sr[k][d]) +
+                          rho[k] * A.g[k][d];
+        }
+        float jx[2], jy[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            jx[k] = mx[k] + 0.5f * F[k][0];
+            jy[k] = my[k] + 0.5f * F[k][1];
+        }
+        const float D = rho[0] * A.it[0] + rho[1] * A.it[1];
+        const float iD = 1.0f / D;
+        const float ux = (jx[0] * A.it[0] + jx[1] * A.it[1]) * iD;
+        const float uy = (jy[0] * A.it[0] + jy[1] * A.it[1]) * iD;
+
+        // The transpose is evaluated in FP64 from the FP32 linearisation point:
+        // for adjoints of conserved or nearly conserved quantities its terms
+        // cancel node by node (the exact adjoint of a conserved functional is
+        // invariant), and FP32 arithmetic there would leave a noise floor on
+        // small gradients.  Only the stored lam is rounded to FP32.
+        using R = double;
+        R lpart[2][9];
+        R Fb[2][2];
+        R gtau[2] = {0.0, 0.0};
+        const R Ux = ux, Uy = uy, UU = (R)ux * ux + (R)uy * uy, ID = (R)1 / ((R)rho[0] * A.it[0] + (R)rho[1] * A.it[1]);
+        if (MODE == 0) {
+            // transpose of streaming (pull of the downstream adjoint)
+            R a[2][9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int yd = y + c_ey[i];
+                const bool bounce = A.walls && (yd < 0 || yd >= A.ny);
+                const int xs = bounce ? x : wrapi(x + c_ex[i], A.nx);
+                const int ys = bounce ? y : wrapi(yd, A.ny);
+                const int is = bounce ? c_op[i] : i;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) a[k][i] = lam_next[xidx(A, k * 9 + is, xs, ys)];
+            }
+            // transpose of Eq. 1 (BGK + Guo) at fixed rho_k, u, F_k
+            R ubx = 0.0, uby = 0.0, rbar[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const R it = A.it[k], c = A.cg[k], Fx = F[k][0], Fy = F[k][1], rk = rho[k];
+                R rb = 0.0, fbx = 0.0, fby = 0.0, gt = 0.0, gg = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const R ex = c_ex[i], ey = c_ey[i], w = (R)wgt9[i];
+                    const R eu = ex * Ux + ey * Uy;
+                    const R eF = ex * Fx + ey * Fy;
+                    const R Em1 = 3.0 * eu + 4.5 * eu * eu - 1.5 * UU;  // E - 1
+                    const R ai = a[k][i];
+                    rb += ai * w * (1.0 + Em1);
+                    const R awr = ai * w * rk * it;
+                    ubx += awr * (3.0 * ex + 9.0 * eu * ex - 3.0 * Ux);
+                    uby += awr * (3.0 * ey + 9.0 * eu * ey - 3.0 * Uy);
+                    const R gx = 3.0 * (ex - Ux) + 9.0 * eu * ex;
+                    const R gy = 3.0 * (ey - Uy) + 9.0 * eu * ey;
+                    fbx += ai * w * gx;
+                    fby += ai * w * gy;
+                    ubx += ai * c * w * (-3.0 * Fx + 9.0 * eF * ex);
+                    uby += ai * c * w * (-3.0 * Fy + 9.0 * eF * ey);
+                    // f - feq in deviation form: dev - w (drho + rho (E - 1))
+                    const R fneq = (R)dev[k][i] - w * ((R)drho[k] + rk * Em1);
+                    gt += ai * fneq;
+                    gg += ai * w * (gx * Fx + gy * Fy);
+                }
+                rbar[k] = rb * it;
+                Fb[k][0] = c * fbx;
+                Fb[k][1] = c * fby;
+                gtau[k] = (gt + 0.5 * gg) * it * it;
+            }
+            // transpose of Eq. 3 and of Eq. 6 (j = m + F/2)
+            R mbx[2], mby[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const R it = A.it[k];
+                const R jbx = ubx * it * ID, jby = uby * it * ID;
+                rbar[k] -= (ubx * Ux + uby * Uy) * it * ID;
+                gtau[k] += (ubx * (Ux * rho[k] - jx[k]) + uby * (Uy * rho[k] - jy[k])) * it * it * ID;
+                mbx[k] = jbx;
+                mby[k] = jby;
+                Fb[k][0] += 0.5 * jbx;
+                Fb[k][1] += 0.5 * jby;
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i)
+                    lpart[k][i] = (1.0 - (R)A.it[k]) * a[k][i] + mbx[k] * (R)c_ex[i] +
+                                  mby[k] * (R)c_ey[i] + rbar[k];
+        } else {
+            // J_Q: u_x = (sum_k m_kx + F_kx / 2) / rho, summed over x and / nx
+            const R rt = (R)rho[0] + rho[1];
+            const R irt = 1.0 / rt;
+            const R ubar = ((R)jx[0] + jx[1]) * irt;
+            acc[5] = ubar * (R)A.qscale;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) lpart[k][i] = (R)A.qscale * ((R)c_ex[i] - ubar) * irt;
+                Fb[k][0] = 0.5 * (R)A.qscale * irt;
+                Fb[k][1] = 0.0;
+            }
+        }
+        // own-node terms of the force transpose and the coupling gradients
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const R s1F = s1[k][0] * Fb[k][0] + s1[k][1] * Fb[k][1];
+            const R s2F = s2[k][0] * Fb[k][0] + s2[k][1] * Fb[k][1];
+            const R srF = sr[k][0] * Fb[k][0] + sr[k][1] * Fb[k][1];
+            const R psibar = -((R)A.G1[k] * s1F + (R)A.G2[k] * s2F);
+            const R rown = psibar * (R)expf(-rho[k] * A.inv_rho0) - (R)A.gab * srF +
+                           (R)A.g[k][0] * Fb[k][0] + (R)A.g[k][1] * Fb[k][1];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) lam[xidx(A, k * 9 + i, x, y)] = (float)(lpart[k][i] + rown);
+            A.scr[sidx(A, SCR_FBAR + 2 * k, x, y)] = (float)Fb[k][0];
+            A.scr[sidx(A, SCR_FBAR + 2 * k + 1, x, y)] = (float)Fb[k][1];
+            acc[0] += -(R)psi[k] * s1F;
+            acc[1] += -(R)psi[k] * s2F;
+            acc[2] += -(R)rho[k] * srF;
+            acc[3 + k] += gtau[k];
+        }
+    }
+    // adjoint steps add into their block's slot (cleared by k_adj_zero before a
+    // run; launches on one stream are ordered, so no two blocks share a slot)
+    block_sum(acc, A.part + (int64_t)block_id() * NPART, MODE == 0);
+}
+
+// clear the per-block partial sums (a kernel, not a memset: graph-safe)
+__global__ __launch_bounds__(256) void k_adj_zero(AdjPar A, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) A.part[i] = 0.0;
+}
+
+// ---------------------------------------------------------------- force transpose
+// Neighbour terms: with q_k = psi_k Fbar_k and r_k = rho_k Fbar_k,
+//   psibar_k(y) = sum_e c_k(e) e . (q_k(y + e) - q_k(y - e))   (e over half of D2Q25,
+//                 c_k(e) = G1_k w(e) + G2_k p(e))
+//   rhobar_kb(y) += G_AB sum_e w(e) e . (r_k(y + e) - r_k(y - e))   (half of D2Q9)
+// and lam_{k,i}(y) += psibar_k(y) exp(-rho_k / rho0) + rhobar_k(y).
+struct QTile {
+    float q[2][2][AH][AW];  // [k][d]
+    float r[2][2][AH][AW];
+};
+
+__global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A, float *__restrict__ lam)
+{
+    __shared__ QTile T;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    for (int t = threadIdx.x; t < AW * AH; t += NTHREADS) {
+        const int lx = t % AW, ly = t / AW;
+        const int gx = wrapi(x0 + lx - HALO, A.nx);
+        const int gy = y0 + ly - HALO;
+        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);  // no force acts there
+        const int yy = ghost ? 0 : wrapi(gy, A.ny);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, gx, yy)];
+            const float p = apsi(A, r);
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const float fb = ghost ? 0.0f : A.scr[sidx(A, SCR_FBAR + 2 * k + d, gx, yy)];
+                T.q[k][d][ly][lx] = p * fb;
+                T.r[k][d][ly][lx] = r * fb;
+            }
+        }
+    }
+    __syncthreads();
+    const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= A.nx || y >= A.ny) return;
+    const int cx = lx + HALO, cy = ly + HALO;
+    float add[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        float ax, ay, bx, by, cx_, cy_, dx_, dy_;
+        auto qx = [&](int dx, int dy) { return T.q[k][0][cy + dy][cx + dx]; };
+        auto qy = [&](int dx, int dy) { return T.q[k][1][cy + dy][cx + dx]; };
+        const float c1 = A.G1[k] * W1 + A.G2[k] * P1, c2 = A.G1[k] * W2 + A.G2[k] * P2;
+        const float c4 = A.G2[k] * P4, c5 = A.G2[k] * P5, c8 = A.G2[k] * P8;
+        sum25<float>(qx, c1, c2, c4, c5, c8, ax, ay);  // uses the x component along e_x, e_y
+        sum25<float>(qy, c1, c2, c4, c5, c8, bx, by);
+        const float psibar = ax + by;  // e . q summed: e_x q_x + e_y q_y
+        // inter-species: r of the other component
+        auto rx = [&](int dx, int dy) { return T.r[1 - k][0][cy + dy][cx + dx]; };
+        auto ry = [&](int dx, int dy) { return T.r[1 - k][1][cy + dy][cx + dx]; };
+        sum9s<float>(rx, W1, W2, cx_, cy_);
+        sum9s<float>(ry, W1, W2, dx_, dy_);
+        const float r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, x, y)];
+        add[k] = psibar * expf(-r * A.inv_rho0) + A.gab * (cx_ + dy_);
+        (void)ay;
+        (void)bx;
+        (void)cy_;
+        (void)dx_;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lam[xidx(A, k * 9 + i, x, y)] += add[k];
+}
+
+// ---------------------------------------------------------------- objectives
+// J_dp sums per block: [0] S_A [1] S_B [2] P_A [3] P_B [4] dP_A/dG12 [5] dP_B/dG12
+// [6] dP_A/dG_AB [7] dP_B/dG_AB (p_b of Eq. 11, weights chi = max(0, +-phi)^4)
+__device__ __forceinline__ float bulk_pressure(const AdjPar &A, float ra, float rb, float pa,
+                                               float pb)
+{
+    return (ra + 0.5f * (A.G1[0] + A.G2[0]) * pa * pa + rb + 0.5f * (A.G1[1] + A.G2[1]) * pb * pb +
+            A.gab * ra * rb) *
+           (1.0f / 3.0f);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_obj_dp_sums(AdjPar A)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < A.nx && y < A.ny) {
+        const float ra = A.rho_ref[0] + A.scr[sidx(A, SCR_RDEV, x, y)];
+        const float rb = A.rho_ref[1] + A.scr[sidx(A, SCR_RDEV + 1, x, y)];
+        const float pa = apsi(A, ra), pb = apsi(A, rb);
+        const float pr = bulk_pressure(A, ra, rb, pa, pb);
+        const float phi = (ra - rb) / (ra + rb);
+        const float p2 = phi * phi;
+        const float ca = phi > 0.0f ? p2 * p2 : 0.0f, cb = phi < 0.0f ? p2 * p2 : 0.0f;
+        const float dG12 = (0.5f / 3.0f) * (pa * pa + pb * pb), dGab = ra * rb * (1.0f / 3.0f);
+        acc[0] = ca;
+        acc[1] = cb;
+        acc[2] = (double)pr * ca;
+        acc[3] = (double)pr * cb;
+        acc[4] = (double)dG12 * ca;
+        acc[5] = (double)dG12 * cb;
+        acc[6] = (double)dGab * ca;
+        acc[7] = (double)dGab * cb;
+    }
+    block_sum(acc, A.part + (int64_t)block_id() * NPART);
+}
+
+// seed of J_dp: dJ/df_{k,i} = dJ/drho_k for every i; m = {<p>_A, <p>_B, S_A, S_B}
+__global__ __launch_bounds__(NTHREADS) void k_obj_dp_seed(AdjPar A, float *__restrict__ lam,
+                                                          float mA, float mB, float iSA, float iSB)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    if (x >= A.nx || y >= A.ny) return;
+    const float ra = A.rho_ref[0] + A.scr[sidx(A, SCR_RDEV, x, y)];
+    const float rb = A.rho_ref[1] + A.scr[sidx(A, SCR_RDEV + 1, x, y)];
+    const float pa = apsi(A, ra), pb = apsi(A, rb);
+    const float pr = bulk_pressure(A, ra, rb, pa, pb);
+    const float s = ra + rb, is2 = 1.0f / (s * s);
+    const float phi = (ra - rb) / s;
+    const float dphi[2] = {2.0f * rb * is2, -2.0f * ra * is2};
+    const float dp[2] = {
+        (1.0f + (A.G1[0] + A.G2[0]) * pa * expf(-ra * A.inv_rho0) + A.gab * rb) * (1.0f / 3.0f),
+        (1.0f + (A.G1[1] + A.G2[1]) * pb * expf(-rb * A.inv_rho0) + A.gab * ra) * (1.0f / 3.0f)};
+    const float p2 = phi * phi;
+    const float ca = phi > 0.0f ? p2 * p2 : 0.0f, cb = phi < 0.0f ? p2 * p2 : 0.0f;
+    const float dca = phi > 0.0f ? 4.0f * p2 * phi : 0.0f, dcb = phi < 0.0f ? 4.0f * p2 * phi : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float d = (dp[k] * ca + (pr - mA) * dca * dphi[k]) * iSA -
+                        (dp[k] * cb + (pr - mB) * dcb * dphi[k]) * iSB;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lam[xidx(A, k * 9 + i, x, y)] = d;
+    }
+}
+
+// linear functionals J = sum c_{k,i} f_{k,i}: which 2 (x-momentum of A),
+// 3 (total x-momentum), 4 (mass of A); block partial slot 5 holds J
+__global__ __launch_bounds__(NTHREADS) void k_obj_lin(AdjPar A, const float *__restrict__ f,
+                                                      float *__restrict__ lam, int which)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (x < A.nx && y < A.ny) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const float c = which == 4 ? (k == 0 ? 1.0f : 0.0f)
+                                           : (which == 2 && k == 1 ? 0.0f : (float)c_ex[i]);
+                const float fi = f[xidx(A, k * 9 + i, x, y)] + wgt(i) * A.rho_ref[k];
+                s += (double)c * (double)fi;
+                if (lam) lam[xidx(A, k * 9 + i, x, y)] = c;
+            }
+        acc[5] = s;
+    }
+    block_sum(acc, A.part + (int64_t)block_id() * NPART);
+}
+
+// Fixed-order sum of the per-block partials into res[0..NPART); if grad is
+// not NULL, grad[0..4] += res[0..4].
+__global__ __launch_bounds__(256) void k_adj_final(AdjPar A, int nblocks, double *__restrict__ grad)
+{
+    __shared__ double red[256];
+    for (int j = 0; j < NPART; ++j) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) s += A.part[(int64_t)b * NPART + j];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            A.res[j] = red[0];
+            if (grad && j < 5) grad[j] += red[0];
+        }
+        __syncthreads();
+    }
+}
+
+dim3 agrid(const AdjPar &A) { return dim3((A.nx + TX - 1) / TX, (A.ny + TY - 1) / TY); }
+int nblk(const AdjPar &A) { return (int)(((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY)); }
+
+}  // namespace
+
+#define LAUNCH_CHECK()                                            \
+    do {                                                          \
+        hipError_t e_ = hipGetLastError();                        \
+        if (e_ != hipSuccess) return e_;                          \
+    } while (0)
+
+hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st)
+{
+    const int n = nblk(A) * NPART;
+    k_adj_zero<<<(n + 255) / 256, 256, 0, st>>>(A, n);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *lam_next, float *lam,
+                               hipStream_t st)
+{
+    k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f);
+    LAUNCH_CHECK();
+    k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam);
+    LAUNCH_CHECK();
+    k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st)
+{
+    k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam_next, float *lam,
+                               double *grad, hipStream_t st)
+{
+    hipError_t e = launch_adjoint_zero(A, st);
+    if (e == hipSuccess) e = launch_adjoint_body(A, f, lam_next, lam, st);
+    if (e == hipSuccess) e = launch_adjoint_final(A, grad, st);
+    return e;
+}
+
+hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, float *lam,
+                                  hipStream_t st)
+{
+    k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f);
+    LAUNCH_CHECK();
+    if (which == 0) {
+        k_obj_dp_sums<<<agrid(A), NTHREADS, 0, st>>>(A);
+    } else if (which == 1) {
+        k_adj_local<1><<<agrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
+        LAUNCH_CHECK();
+        k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam);
+    } else {
+        k_obj_lin<<<agrid(A), NTHREADS, 0, st>>>(A, f, lam, which);
+    }
+    LAUNCH_CHECK();
+    k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), nullptr);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_objective_dp_seed(const AdjPar &A, float *lam, double mA, double mB, double SA,
+                                    double SB, hipStream_t st)
+{
+    k_obj_dp_seed<<<agrid(A), NTHREADS, 0, st>>>(A, lam, (float)mA, (float)mB, (float)(1.0 / SA),
+                                                 (float)(1.0 / SB));
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+int adjoint_blocks(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY); }
+
+const char *adjoint_kernel_name(int j)
+{
+    static const char *names[] = {"k_adj_density", "k_adj_local", "k_adj_force", "k_adj_final"};
+    return j >= 0 && j < 4 ? names[j] : "";
+}
+
+hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const float *lam_next,
+                                 float *lam, double *grad, hipStream_t st)
+{
+    switch (j) {
+    case 0: k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f); break;
+    // (the timed local pass accumulates into its partial slots; cleared before use)
+    case 1: k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
+    case 2: k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam); break;
+    default: k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad); break;
+    }
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+}  // namespace lbm

@@ -583,6 +583,220 @@ int lbm_destroy(lbm_ctx *ctx)
     return LBM_OK;
 }
 
+// ------------------------------------------------------------------ adjoint
+static AdjPar adj_par(const lbm_ctx *ctx, int inst)
+{
+    const lbm_params &p = ctx->params[inst];
+    const KInst &K = ctx->hinst[inst];
+    AdjPar A;
+    std::memset(&A, 0, sizeof A);
+    A.nx = p.nx;
+    A.ny = p.ny;
+    A.walls = p.walls;
+    A.pitch = K.pitch;
+    A.plane = K.plane;
+    for (int k = 0; k < 2; ++k) {
+        A.G1[k] = (float)p.G1[k];
+        A.G2[k] = (float)p.G2[k];
+        A.it[k] = (float)(1.0 / p.tau[k]);
+        A.cg[k] = (float)(1.0 - 0.5 / p.tau[k]);
+        A.g[k][0] = (float)p.g[k][0];
+        A.g[k][1] = (float)p.g[k][1];
+        A.rho_ref[k] = K.rho_ref[k];
+        A.rho_wall[k] = K.rho_wall[k];
+        A.psi_wall[k] = K.psi_wall[k];
+    }
+    A.gab = (float)p.G_AB;
+    A.rho0 = K.rho0;
+    A.inv_rho0 = K.inv_rho0;
+    A.qscale = (float)(1.0 / p.nx);
+    A.scr = K.fld;
+    A.part = (double *)(K.fld + (int64_t)SCR_PART * K.plane);
+    A.res = A.part + (int64_t)adjoint_blocks(p.nx, p.ny) * NPART;
+    return A;
+}
+
+static bool overlaps(const void *a, const void *b, uint64_t n)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + n && y < x + n;
+}
+
+int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
+                     float *lam_out_dev, double *grad_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!f_dev || !lam_in_dev || !lam_out_dev) return fail(ctx, LBM_EINVAL, "null argument");
+    const lbm_params &p = ctx->params[inst];
+    const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
+    if (overlaps(lam_out_dev, lam_in_dev, nb) || overlaps(lam_out_dev, f_dev, nb))
+        return fail(ctx, LBM_EINVAL, "lam_out must not overlap f or lam_in");
+    hipError_t e = launch_adjoint_step(adj_par(ctx, inst), f_dev, lam_in_dev, lam_out_dev, grad_dev,
+                                       ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "adjoint kernels");
+    return LBM_OK;
+}
+
+int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (nsteps < 0 || (nsteps > 0 && !f_store_dev)) return fail(ctx, LBM_EINVAL, "bad arguments");
+    const lbm_params &p = ctx->params[inst];
+    const int64_t N = (int64_t)18 * p.nx * p.ny;
+    for (int64_t j = 0; j < nsteps; ++j) {
+        hipError_t e = launch_export(ctx->dev, inst, ctx->par, f_store_dev + j * N, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "export kernel");
+        e = launch_step(ctx->dev, ctx->par, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+        ctx->par ^= 1;
+    }
+    ctx->steps += nsteps;
+    return LBM_OK;
+}
+
+int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_store_dev,
+                    float *lam_dev, float *tmp_dev, double *grad_dev)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (nsteps < 0 || !lam_dev || !tmp_dev || (nsteps > 0 && !f_store_dev))
+        return fail(ctx, LBM_EINVAL, "bad arguments");
+    const lbm_params &p = ctx->params[inst];
+    const int64_t N = (int64_t)18 * p.nx * p.ny;
+    const uint64_t nb = (uint64_t)N * sizeof(float);
+    if (overlaps(lam_dev, tmp_dev, nb)) return fail(ctx, LBM_EINVAL, "lam and tmp overlap");
+    if (nsteps > 0 && (overlaps(lam_dev, f_store_dev, nb * nsteps) ||
+                       overlaps(tmp_dev, f_store_dev, nb * nsteps)))
+        return fail(ctx, LBM_EINVAL, "lam or tmp overlaps the state store");
+    if (nsteps == 0) return LBM_OK;
+    const AdjPar A = adj_par(ctx, inst);
+    hipStream_t st = ctx->stream;
+    hipError_t e = launch_adjoint_zero(A, st);
+    float *cur = lam_dev, *nxt = tmp_dev;
+    for (int64_t j = nsteps - 1; j >= 0 && e == hipSuccess; --j) {
+        e = launch_adjoint_body(A, f_store_dev + j * N, cur, nxt, st);
+        std::swap(cur, nxt);
+    }
+    if (e == hipSuccess) e = launch_adjoint_final(A, grad_dev, st);
+    if (e == hipSuccess && cur != lam_dev)
+        e = hipMemcpyAsync(lam_dev, cur, nb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "adjoint run");
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, int32_t objective, const float *f_dev,
+                     float *lam_dev, double *J, double *dtheta)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!f_dev || !J || !dtheta) return fail(ctx, LBM_EINVAL, "null argument");
+    if (objective < LBM_OBJ_DP || objective > LBM_OBJ_MASS_A)
+        return fail(ctx, LBM_EINVAL, "unknown objective");
+    if (!lam_dev && objective == LBM_OBJ_Q)
+        return fail(ctx, LBM_EINVAL, "the flow-rate objective needs lam_dev");
+    const lbm_params &p = ctx->params[inst];
+    const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
+    if (lam_dev && overlaps(lam_dev, f_dev, nb))
+        return fail(ctx, LBM_EINVAL, "lam_dev must not overlap f_dev");
+    const AdjPar A = adj_par(ctx, inst);
+    hipStream_t st = ctx->stream;
+    hipError_t e = launch_objective_pass1(A, objective, f_dev, lam_dev, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "objective kernels");
+    double res[NPART];
+    HIP_TRY(ctx, hipMemcpyAsync(res, A.res, sizeof res, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int t = 0; t < 5; ++t) dtheta[t] = 0.0;
+    if (objective == LBM_OBJ_DP) {
+        // res: S_A, S_B, P_A, P_B, dP_A/dG12, dP_B/dG12, dP_A/dG_AB, dP_B/dG_AB
+        if (!(res[0] > 0.0) || !(res[1] > 0.0))
+            return fail(ctx, LBM_EINVAL, "pressure-jump objective needs both phases present");
+        const double mA = res[2] / res[0], mB = res[3] / res[1];
+        *J = mA - mB;
+        dtheta[0] = dtheta[1] = res[4] / res[0] - res[5] / res[1];
+        dtheta[2] = res[6] / res[0] - res[7] / res[1];
+        if (lam_dev) {
+            e = launch_objective_dp_seed(A, lam_dev, mA, mB, res[0], res[1], st);
+            if (e != hipSuccess) return hip_fail(ctx, e, "objective seed kernel");
+        }
+    } else {
+        *J = res[5];
+        if (objective == LBM_OBJ_Q)
+            for (int t = 0; t < 3; ++t) dtheta[t] = res[t];
+    }
+    if (!std::isfinite(*J)) return fail(ctx, LBM_ENONFINITE, "objective is not finite");
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_ctx *ctx, int32_t inst, const lbm_params *params)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!params) return fail(ctx, LBM_EINVAL, "null argument");
+    std::string m = check_params(*params);
+    if (!m.empty()) return fail(ctx, LBM_EINVAL, m);
+    const lbm_params &old = ctx->params[inst];
+    if (params->nx != old.nx || params->ny != old.ny || params->walls != old.walls ||
+        (float)params->rho_ref[0] != (float)old.rho_ref[0] ||
+        (float)params->rho_ref[1] != (float)old.rho_ref[1])
+        return fail(ctx, LBM_EINVAL, "nx, ny, walls and rho_ref of an instance cannot change");
+    const InstLayout &L = ctx->layout.inst[inst];
+    KInst K = make_kinst(*params, L, ctx->ws + ctx->layout.off_inst[inst]);
+    // kernels already queued read the old block: order the update after them
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.insts + inst, &K, sizeof K, hipMemcpyHostToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->params[inst] = *params;
+    ctx->hinst[inst] = K;
+    return LBM_OK;
+}
+
+int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
+                        float *lam_out_dev, double *grad_dev, int32_t nrep, int32_t max_k,
+                        double *ms, const char **names, int32_t *n_kernels)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!f_dev || !lam_in_dev || !lam_out_dev || !grad_dev || nrep < 1 || !ms || !n_kernels ||
+        max_k < 0)
+        return fail(ctx, LBM_EINVAL, "bad arguments");
+    const AdjPar A = adj_par(ctx, inst);
+    hipStream_t st = ctx->stream;
+    *n_kernels = N_ADJ_KERNELS;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    rc = LBM_OK;
+    for (int j = 0; j < N_ADJ_KERNELS && j < max_k && rc == LBM_OK; ++j) {
+        hipError_t e = launch_adjoint_zero(A, st);
+        if (e == hipSuccess) e = launch_adjoint_kernel(A, j, f_dev, lam_in_dev, lam_out_dev, grad_dev, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < nrep && e == hipSuccess; ++r)
+            e = launch_adjoint_kernel(A, j, f_dev, lam_in_dev, lam_out_dev, grad_dev, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_fail(ctx, e, "profile launches");
+            break;
+        }
+        ms[j] = (double)t / nrep;
+        if (names) names[j] = adjoint_kernel_name(j);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 const char *lbm_last_error(const lbm_ctx *ctx)
 {
     return ctx ? ctx->err.c_str() : g_init_error.c_str();

@@ -37,6 +37,49 @@ hipError_t launch_forces(const Dev &d, int inst, int par, const float *rho, floa
 hipError_t launch_observables(const Dev &d, int par, double margin, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t st);
 
+// ------------------------------------------------------------------ adjoint
+// Scratch planes of the instance's field region used by the adjoint passes:
+// density deviations (2), force adjoints [k][d] (4), then FP64 block partials
+// (NPART per 64 x 4 tile) followed by NPART final sums.
+constexpr int SCR_RDEV = 0;
+constexpr int SCR_FBAR = 2;
+constexpr int SCR_PART = 6;
+constexpr int NPART = 8;
+
+// Parameters of one instance for the adjoint kernels (passed by value).
+struct AdjPar {
+    int32_t nx, ny, walls, pitch;
+    int64_t plane;          // floats between scratch planes
+    float G1[2], G2[2];     // Eq. 8 couplings per component
+    float gab;              // Eq. 9 coupling
+    float it[2];            // 1 / tau_k
+    float cg[2];            // 1 - 1 / (2 tau_k), Guo prefactor of Eq. 5
+    float g[2][2];          // body acceleration per component
+    float rho_ref[2], rho_wall[2], psi_wall[2];
+    float rho0, inv_rho0;
+    float qscale;           // 1 / nx (flow-rate objective)
+    float *scr;             // scratch planes
+    double *part;           // [blocks][NPART]
+    double *res;            // [NPART]
+};
+
+hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam_next, float *lam,
+                               double *grad, hipStream_t st);
+// pieces of a run of adjoint steps: clear the partials, one step, final sums
+hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st);
+hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *lam_next, float *lam,
+                               hipStream_t st);
+hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st);
+hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, float *lam,
+                                  hipStream_t st);
+hipError_t launch_objective_dp_seed(const AdjPar &A, float *lam, double mA, double mB, double SA,
+                                    double SB, hipStream_t st);
+int adjoint_blocks(int nx, int ny);
+constexpr int N_ADJ_KERNELS = 4;
+const char *adjoint_kernel_name(int j);
+hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const float *lam_next,
+                                 float *lam, double *grad, hipStream_t st);
+
 // kernels of one step, for timing: number, names, and a launcher of kernel j
 constexpr int N_STEP_KERNELS = 1;
 const char *step_kernel_name(int j);

@@ -22,6 +22,16 @@ LBM_EHIP = -2
 LBM_ENONFINITE = -3
 LBM_EUNSUPPORTED = -4
 
+# objectives of lbm_adjoint_seed
+LBM_OBJ_DP = 0
+LBM_OBJ_Q = 1
+LBM_OBJ_MOM_A = 2
+LBM_OBJ_MOM = 3
+LBM_OBJ_MASS_A = 4
+OBJECTIVES = {"dp": LBM_OBJ_DP, "Q": LBM_OBJ_Q, "momA": LBM_OBJ_MOM_A, "mom": LBM_OBJ_MOM,
+              "massA": LBM_OBJ_MASS_A}
+THETA_NAMES = ("G1", "G2", "G_AB", "tau_A", "tau_B")
+
 
 class lbm_params(ctypes.Structure):
     _fields_ = [
@@ -89,6 +99,15 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_tiling.argtypes = [vp, ctypes.c_int32]
         L.lbm_get_tiling.argtypes = [vp]
         L.lbm_get_tiling.restype = ctypes.c_int32
+        L.lbm_adjoint_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
+        L.lbm_adjoint_seed.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                       P(ctypes.c_double), P(ctypes.c_double)]
+        L.lbm_set_params.argtypes = [vp, ctypes.c_int32, P(lbm_params)]
+        L.lbm_record.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp]
+        L.lbm_adjoint_run.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp]
+        L.lbm_profile_adjoint.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
+                                          ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_char_p),
+                                          P(ctypes.c_int32)]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
@@ -202,6 +221,48 @@ def lbm_get_tiling(ctx) -> int:
     return int(lib().lbm_get_tiling(ctx))
 
 
+def lbm_adjoint_step(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr: int,
+                     grad_ptr: int | None):
+    _check(lib().lbm_adjoint_step(ctx, inst, ctypes.c_void_p(f_ptr), ctypes.c_void_p(lam_in_ptr),
+                                  ctypes.c_void_p(lam_out_ptr), ctypes.c_void_p(grad_ptr)), ctx)
+
+
+def lbm_adjoint_seed(ctx, inst: int, objective: int, f_ptr: int, lam_ptr: int | None):
+    """(J, direct dJ/dtheta as a numpy array of 5)."""
+    J = ctypes.c_double()
+    dth = (ctypes.c_double * 5)()
+    _check(lib().lbm_adjoint_seed(ctx, inst, int(objective), ctypes.c_void_p(f_ptr),
+                                  ctypes.c_void_p(lam_ptr), ctypes.byref(J), dth), ctx)
+    return float(J.value), np.array(list(dth))
+
+
+def lbm_record(ctx, inst: int, nsteps: int, f_store_ptr: int):
+    _check(lib().lbm_record(ctx, inst, int(nsteps), ctypes.c_void_p(f_store_ptr)), ctx)
+
+
+def lbm_adjoint_run(ctx, inst: int, nsteps: int, f_store_ptr: int, lam_ptr: int, tmp_ptr: int,
+                    grad_ptr: int | None):
+    _check(lib().lbm_adjoint_run(ctx, inst, int(nsteps), ctypes.c_void_p(f_store_ptr),
+                                 ctypes.c_void_p(lam_ptr), ctypes.c_void_p(tmp_ptr),
+                                 ctypes.c_void_p(grad_ptr)), ctx)
+
+
+def lbm_set_params(ctx, inst: int, params: lbm_params):
+    _check(lib().lbm_set_params(ctx, inst, ctypes.byref(params)), ctx)
+
+
+def lbm_profile_adjoint(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr: int,
+                        grad_ptr: int, nrep: int, max_k: int = 8):
+    ms = (ctypes.c_double * max_k)()
+    names = (ctypes.c_char_p * max_k)()
+    nk = ctypes.c_int32()
+    _check(lib().lbm_profile_adjoint(ctx, inst, ctypes.c_void_p(f_ptr), ctypes.c_void_p(lam_in_ptr),
+                                     ctypes.c_void_p(lam_out_ptr), ctypes.c_void_p(grad_ptr),
+                                     int(nrep), max_k, ms, names, ctypes.byref(nk)), ctx)
+    n = min(nk.value, max_k)
+    return [(names[j].decode(), ms[j]) for j in range(n)]
+
+
 def lbm_destroy(ctx):
     _check(lib().lbm_destroy(ctx), None)
 
@@ -280,8 +341,41 @@ class Sim:
         w = np.array([16, 4, 4, 4, 4, 1, 1, 1, 1], dtype=np.float64) / 36.0
         return f + w[None, :, None, None] * np.asarray(p.rho_ref[:])[:, None, None, None]
 
+    def populations_into(self, f_dev, inst: int = 0):
+        """Export the populations into a contiguous [2, 9, ny, nx] FP32 device tensor (async)."""
+        assert f_dev.is_contiguous() and f_dev.dtype == self.torch.float32
+        lbm_get_populations(self.ctx, inst, f_dev.data_ptr())
+
     def set_populations(self, f_dev, inst: int = 0):
         lbm_set_populations(self.ctx, inst, f_dev.data_ptr())
+
+    # --------------------------------------------------------------- parameters and adjoint
+    def theta(self, inst: int = 0) -> np.ndarray:
+        """theta = (G1, G2, G_AB, tau_A, tau_B) of an instance (component A's G1, G2)."""
+        p = self.params[inst]
+        return np.array([p.G1[0], p.G2[0], p.G_AB, p.tau[0], p.tau[1]], dtype=np.float64)
+
+    def set_theta(self, theta, inst: int = 0):
+        """Set G1, G2 (both components), G_AB, tau_A, tau_B of an instance."""
+        t = [float(v) for v in theta]
+        p = lbm_params.from_buffer_copy(self.params[inst])
+        p.G1[:] = (t[0], t[0])
+        p.G2[:] = (t[1], t[1])
+        p.G_AB = t[2]
+        p.tau[:] = (t[3], t[4])
+        lbm_set_params(self.ctx, inst, p)
+        self.params[inst] = p
+
+    def adjoint_step(self, f_dev, lam_in, lam_out, grad_dev=None, inst: int = 0):
+        """lam_out = (df(t+1)/df(t))^T lam_in at state f_dev; grad_dev += theta part (async)."""
+        lbm_adjoint_step(self.ctx, inst, f_dev.data_ptr(), lam_in.data_ptr(), lam_out.data_ptr(),
+                         None if grad_dev is None else grad_dev.data_ptr())
+
+    def adjoint_seed(self, objective, f_dev, lam_dev=None, inst: int = 0):
+        """(J, direct dJ/dtheta) of state f_dev; lam_dev receives dJ/df."""
+        obj = OBJECTIVES[objective] if isinstance(objective, str) else int(objective)
+        return lbm_adjoint_seed(self.ctx, inst, obj, f_dev.data_ptr(),
+                                None if lam_dev is None else lam_dev.data_ptr())
 
     def forces(self, rho_dev, inst: int = 0):
         p = self.params[inst]
