@@ -43,13 +43,13 @@ DOMINANT = "k_fused_step"
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
 # library), valid only for the kernel sources and strip height they were
 # measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "8678cac69f1ae8a9", "strip_height": 48,
+MEASURED_TRAFFIC = {"src_sha256_16": "8678cac69f1ae8a9", "strip_height": 48, "strip_width": 62,
                     "fetch_bytes": 180225.7 * 2.0 * 1024, "write_bytes": 351596.4 * 1.0 * 1024}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
 
-def measured_traffic(strip_height):
+def measured_traffic(strip_width, strip_height):
     """Counter-based bytes per launch, or None once the kernel or its launch shape changed."""
     import hashlib
     h = hashlib.sha256()
@@ -57,7 +57,8 @@ def measured_traffic(strip_height):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     t = MEASURED_TRAFFIC
-    if h.hexdigest()[:16] != t["src_sha256_16"] or strip_height != t["strip_height"]:
+    if (h.hexdigest()[:16] != t["src_sha256_16"] or strip_height != t["strip_height"]
+            or strip_width != t["strip_width"]):
         return None
     return round(t["fetch_bytes"] + t["write_bytes"])
 
@@ -72,6 +73,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~15 s)")
     ap.add_argument("--chunk", type=int, default=0, help="strip height (0: autotune)")
+    ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 62)")
     ap.add_argument("--batched-steps", type=int, default=1000, help="0 skips the batched form")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint form")
     ap.add_argument("--adjoint-window", type=int, default=200)
@@ -133,7 +135,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     ms_fwd = timed(torch, fwd.stream, lambda: fwd.step(steps))
     fwd.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
-    lbm.lbm_set_tiling(prob.sim.ctx, int(tuning["best"]))
+    tune.apply(prob.sim, tuning["width"], tuning["best"])
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -158,7 +160,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     return {"workload": f"{w.nx}x{w.ny} periodic, 16 droplets R=20, g_x=1e-6, "
                         "couplings (3.0, -7.4, 6.4), tau (1.0, 0.6)",
             "steps": steps, "window": window, "objective": "J_dp (smooth pressure jump)",
-            "strip_height": tuning["best"],
+            "strip_shape": [tuning["width"], tuning["best"]],
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),
             "J": J, "grad_theta": {n: float(v) for n, v in zip(lbm.THETA_NAMES, g)},
@@ -205,8 +207,8 @@ def main():
 
     # strip height: autotuned (untimed) unless given
     if a.chunk > 0:
-        lbm.lbm_set_tiling(sim.ctx, a.chunk)
-        tuning = {"best": a.chunk}
+        tune.apply(sim, a.width or 62, a.chunk)
+        tuning = {"best": a.chunk, "width": a.width or 62}
     else:
         tuning = tune.tune(sim, use_cache=False)
 
@@ -263,7 +265,7 @@ def main():
     adj = bench_adjoint(torch, lbm, W, a.adjoint_steps, a.adjoint_window) if a.adjoint_steps > 0 else None
 
     cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
-    traffic = measured_traffic(lbm.lbm_get_tiling(sim.ctx))
+    traffic = measured_traffic(lbm.lbm_get_strip_width(sim.ctx), lbm.lbm_get_tiling(sim.ctx))
 
     mass_drift = [abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] for k in range(2)]
     out = {

@@ -10,7 +10,7 @@
 // Buffers are the caller's, in the population export layout [2][9][ny][nx]
 // (FP32 deviations f - w_i rho_ref for the state; plain FP32 for lam).  One
 // adjoint step is three passes over 64 x 4 tiles:
-//   k_adj_density  density deviations of f (TwoSum, as the forward step)
+//   k_adj_density  density deviations of f (rounded as the forward step's)
 //                  into scratch plane pair rdev;
 //   k_adj_local    per node: recompute rho, psi, the stencil sums of Eqs. 8
 //                  and 9 (LDS tile with a halo of 2), F, j, u^eq; gather
@@ -139,11 +139,10 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_density(AdjPar A, const float 
     if (x >= A.nx || y >= A.ny) return;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        float v[9], hi, lo;
+        float v[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = f[xidx(A, k * 9 + i, x, y)];
-        sum9(v, hi, lo);
-        A.scr[sidx(A, SCR_RDEV + k, x, y)] = hi + lo;
+        A.scr[sidx(A, SCR_RDEV + k, x, y)] = sum9(v);
     }
 }
 

@@ -1,5 +1,6 @@
 // C-ABI entry points (include/lbm.h): validation, workspace layout, context
 // bookkeeping and HIP-graph replay of the step loop.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +18,8 @@ constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: parity uncha
 constexpr uint64_t ALIGN = 256;
 constexpr int MIN_CHUNK = 4;     // smallest strip height the workspace is sized for
 constexpr int DEFAULT_CHUNK = 16;
+constexpr int MIN_WIDTH = 16;    // narrowest strip the workspace is sized for
+constexpr int DEFAULT_WIDTH = SWO;
 
 thread_local std::string g_init_error;
 
@@ -54,22 +57,27 @@ struct Layout {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Strips of the fused step for strip height H: per instance, columns are
-// split into ceil(nx / 62) strips of balanced width and rows into
-// ceil(ny / H) chunks of balanced height.  The table is then ordered so that
-// consecutive workgroup indices, which the hardware deals round-robin to the
-// eight XCDs, give each XCD a contiguous run of neighbouring strips (shared
-// halo columns and rows stay in that XCD's L2).
-std::vector<int4> make_strips(const lbm_params *p, int n, int H)
+// Strips of the fused step for strip height H and output width W (<= 62):
+// per instance, rows are split into ceil(ny / H) chunks of balanced height;
+// columns into ceil(nx / W) strips, either of balanced width (W not a
+// multiple of 16) or starting at multiples of W (W a multiple of 16), so
+// that every output row segment starts on a 64-byte boundary (the writes of
+// neighbouring strips then never share a 64-byte block).  The table is then
+// ordered so that consecutive workgroup indices, which the hardware deals
+// round-robin to the eight XCDs, give each XCD a contiguous run of
+// neighbouring strips (shared halo columns and rows stay in that XCD's L2).
+std::vector<int4> make_strips(const lbm_params *p, int n, int H, int W)
 {
     std::vector<int4> tab;
+    const bool aligned = W % 16 == 0;
     for (int i = 0; i < n; ++i) {
-        const int ns = ceil_div(p[i].nx, SWO), nc = ceil_div(p[i].ny, H);
+        const int ns = ceil_div(p[i].nx, W), nc = ceil_div(p[i].ny, H);
         for (int c = 0; c < nc; ++c) {
             const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
             for (int sx = 0; sx < ns; ++sx) {
-                const int x0 = (int)((int64_t)p[i].nx * sx / ns);
-                const int x1 = (int)((int64_t)p[i].nx * (sx + 1) / ns);
+                const int x0 = aligned ? W * sx : (int)((int64_t)p[i].nx * sx / ns);
+                const int x1 = aligned ? std::min(p[i].nx, W * (sx + 1))
+                                       : (int)((int64_t)p[i].nx * (sx + 1) / ns);
                 tab.push_back(make_int4(i, x0, y0, (x1 - x0) | ((y1 - y0) << 16)));
             }
         }
@@ -87,7 +95,7 @@ std::vector<int4> make_strips(const lbm_params *p, int n, int H)
 int max_strips(const lbm_params *p, int n)
 {
     int t = 0;
-    for (int i = 0; i < n; ++i) t += ceil_div(p[i].nx, SWO) * ceil_div(p[i].ny, MIN_CHUNK);
+    for (int i = 0; i < n; ++i) t += ceil_div(p[i].nx, MIN_WIDTH) * ceil_div(p[i].ny, MIN_CHUNK);
     return t;
 }
 
@@ -202,6 +210,7 @@ struct lbm_ctx {
     int64_t steps = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int chunk = DEFAULT_CHUNK;
+    int width = DEFAULT_WIDTH;
     std::string err;
 };
 
@@ -294,7 +303,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.ninst = n_inst;
     d.ntiles = L.ntiles;
     d.nrows = L.nrows;
-    std::vector<int4> strips = make_strips(params, n_inst, ctx->chunk);
+    std::vector<int4> strips = make_strips(params, n_inst, ctx->chunk, ctx->width);
     d.nstrips = (int)strips.size();
 
     hipStream_t st = ctx->stream;
@@ -549,19 +558,17 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     return rc;
 }
 
-int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
+static int set_strips(lbm_ctx *ctx, int rows, int cols)
 {
-    CTX_CHECK(ctx);
-    if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
-        return fail(ctx, LBM_EINVAL, "chunk_rows must be in [4, 65535]");
-    std::vector<int4> strips = make_strips(ctx->params.data(), ctx->n_inst, chunk_rows);
+    std::vector<int4> strips = make_strips(ctx->params.data(), ctx->n_inst, rows, cols);
     if ((int)strips.size() > ctx->layout.max_strips) return fail(ctx, LBM_EINVAL, "strip table overflow");
     // the table is read by kernels already queued: order the copy after them
     HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, strips.data(), sizeof(int4) * strips.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->dev.nstrips = (int)strips.size();
-    ctx->chunk = chunk_rows;
+    ctx->chunk = rows;
+    ctx->width = cols;
     for (int i = 0; i < 2; ++i)
         if (ctx->graph[i]) {
             (void)hipGraphExecDestroy(ctx->graph[i]);
@@ -569,6 +576,23 @@ int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
         }
     return LBM_OK;
 }
+
+int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
+{
+    CTX_CHECK(ctx);
+    if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
+        return fail(ctx, LBM_EINVAL, "chunk_rows must be in [4, 65535]");
+    return set_strips(ctx, chunk_rows, ctx->width);
+}
+
+int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
+{
+    CTX_CHECK(ctx);
+    if (cols < MIN_WIDTH || cols > SWO) return fail(ctx, LBM_EINVAL, "cols must be in [16, 62]");
+    return set_strips(ctx, ctx->chunk, cols);
+}
+
+int32_t lbm_get_strip_width(const lbm_ctx *ctx) { return ctx ? ctx->width : -1; }
 
 int32_t lbm_get_tiling(const lbm_ctx *ctx) { return ctx ? ctx->chunk : -1; }
 

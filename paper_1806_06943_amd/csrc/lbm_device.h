@@ -4,8 +4,8 @@
 //
 // Storage: the state at time t is the post-streaming, pre-collision
 // populations f(t) as FP32 deviations f - w_i rho_ref, plus their density
-// deviations sum_i (f_i - w_i rho_ref), correctly rounded from the exact sum
-// (double-buffered with those of t+1).  The collision needs exactly that
+// deviations sum_i (f_i - w_i rho_ref), correctly rounded (double-buffered
+// with those of t+1).  The collision needs exactly that
 // rounded sum, so the step reads it instead of summing again.
 //
 // Layout: row-major rows of population segments, f[y][q][x] with q = 9 k + i
@@ -15,8 +15,8 @@
 // pages are reused instead of 36 planes megabytes apart being streamed.
 //
 // Numerical formulation (FP32 throughout the step):
-//   * the density deviation sum uses error-free TwoSum accumulation, so the
-//     rest-state part of the collision sees the stored mass exactly;
+//   * the density deviation sum is accumulated in FP64 and rounded once, so
+//     the rest-state part of the collision sees the stored mass exactly;
 //   * weights are w_i = c_i / 36 with integer c_i = 16, 4, 1; quantities per
 //     unit weight are formed by a correctly rounded division by 36, so the
 //     rounding of the weights cannot create or destroy mass systematically;
@@ -134,20 +134,15 @@ __device__ __forceinline__ void load_node(const KInst &P, const float *__restric
         for (int i = 0; i < 9; ++i) f[k][i] = fb[fidx(P, k * 9 + i, x, y)];
 }
 
-// Error-free sum of the nine deviations: drho = hi + lo exactly up to the
-// final representation (Knuth TwoSum per term).
-__device__ __forceinline__ void sum9(const float f[9], float &hi, float &lo)
+// Sum of the nine deviations, correctly rounded to FP32: the FP32 terms are
+// added in FP64 (exactly, unless their exponents span more than 29 bits)
+// and the total is rounded once.
+__device__ __forceinline__ float sum9(const float f[9])
 {
-    float s = f[0], c = 0.0f;
+    double s = (double)f[0];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const float t = s + f[i];
-        const float bp = t - s;
-        c += (s - (t - bp)) + (f[i] - bp);
-        s = t;
-    }
-    hi = s;
-    lo = c;
+    for (int i = 1; i < 9; ++i) s += (double)f[i];
+    return (float)s;
 }
 
 // LDS density tile: rho and psi of both components on the tile plus a halo

@@ -45,11 +45,7 @@ __global__ __launch_bounds__(NTHREADS) void k_density(const KInst *__restrict__ 
     float f[2][9];
     load_node(P, P.f[par], x, y, f);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        float hi, lo;
-        sum9(f[k], hi, lo);
-        P.rho[par][ridx(P, k, x, y)] = hi + lo;
-    }
+    for (int k = 0; k < 2; ++k) P.rho[par][ridx(P, k, x, y)] = sum9(f[k]);
 }
 
 // ------------------------------------------------------------------ fused step
@@ -134,6 +130,11 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
     const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + l, nx) * 4u;
     const int xe = l & 3, ke = (l >> 2) & 1;
     const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + SW + xe, nx) * 4u + (ke ? qb : 0u);
+    // per-lane parameters of the extra column's component, selected once (a
+    // lane-dependent index into the parameter copy would put it in scratch)
+    const float ref_e = ke ? P.rho_ref[1] : P.rho_ref[0];
+    const float rwall_e = ke ? P.rho_wall[1] : P.rho_wall[0];
+    const float pwall_e = ke ? P.psi_wall[1] : P.psi_wall[0];
 
     // lattice row r -> wrapped row index, or -1 beyond a wall (general
     // form, used once per cursor); cursors then advance by one row
@@ -173,10 +174,10 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
         R.psi[1][slot][l] = wall ? P.psi_wall[1] : psi_of(P, rb);
         R.dev[0][slot][l] = v.a;
         R.dev[1][slot][l] = v.b;
-        const float re = wall ? P.rho_wall[ke] : P.rho_ref[ke] + v.e;
+        const float re = wall ? rwall_e : ref_e + v.e;
         R.dev[ke][slot][SW + xe] = v.e;
         R.rho[ke][slot][SW + xe] = re;
-        R.psi[ke][slot][SW + xe] = wall ? P.psi_wall[ke] : psi_of(P, re);
+        R.psi[ke][slot][SW + xe] = wall ? pwall_e : psi_of(P, re);
     };
     auto load_f = [&](int ri, float f[2][9]) {
         const uint32_t off = (uint32_t)(ri < 0 ? 0 : ri) * frowb + xcb;
@@ -274,9 +275,7 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
                 g[8] = whi ? Sprev[k][6] : d8;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) bstore(g[i], fout, off, (uint32_t)(k * 9 + i) * qb);
-                float hi, lo;
-                sum9(g, hi, lo);
-                bstore(hi + lo, rout, roff, (uint32_t)k * qb);
+                bstore(sum9(g), rout, roff, (uint32_t)k * qb);
             }
         }
 #pragma unroll

@@ -99,6 +99,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_tiling.argtypes = [vp, ctypes.c_int32]
         L.lbm_get_tiling.argtypes = [vp]
         L.lbm_get_tiling.restype = ctypes.c_int32
+        L.lbm_set_strip_width.argtypes = [vp, ctypes.c_int32]
+        L.lbm_get_strip_width.argtypes = [vp]
+        L.lbm_get_strip_width.restype = ctypes.c_int32
         L.lbm_adjoint_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
         L.lbm_adjoint_seed.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp,
                                        P(ctypes.c_double), P(ctypes.c_double)]
@@ -219,6 +222,14 @@ def lbm_set_tiling(ctx, chunk_rows: int):
 
 def lbm_get_tiling(ctx) -> int:
     return int(lib().lbm_get_tiling(ctx))
+
+
+def lbm_set_strip_width(ctx, cols: int):
+    _check(lib().lbm_set_strip_width(ctx, int(cols)), ctx)
+
+
+def lbm_get_strip_width(ctx) -> int:
+    return int(lib().lbm_get_strip_width(ctx))
 
 
 def lbm_adjoint_step(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr: int,
