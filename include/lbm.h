@@ -160,12 +160,13 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
 int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows);
 int32_t lbm_get_tiling(const lbm_ctx *ctx);
 
-/* Output columns per strip of the fused step, in [16, 62] (default 62).  A
- * multiple of 16 places strips at multiples of cols, so that every row of
- * output starts on a 64-byte boundary (fewer partial writes, more strips);
- * any other value splits each row into ceil(nx / cols) strips of balanced
- * width.  Results are bitwise identical for every value.  Synchronises the
- * stream and discards captured graphs. */
+/* Output columns per strip of the fused step, in [16, 510] (default 62).  A
+ * strip is one workgroup of 1, 2, 4 or 8 wavefronts (up to 62, 126, 254 or
+ * 510 columns).  A multiple of 16 places strips at multiples of cols, so
+ * that every row of output starts on a 64-byte boundary; any other value
+ * splits each row into ceil(nx / cols) strips of balanced width.  Results
+ * are bitwise identical for every value.  Synchronises the stream and
+ * discards captured graphs. */
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols);
 int32_t lbm_get_strip_width(const lbm_ctx *ctx);
 

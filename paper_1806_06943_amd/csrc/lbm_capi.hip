@@ -57,7 +57,8 @@ struct Layout {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Strips of the fused step for strip height H and output width W (<= 62):
+// Strips of the fused step for strip height H and output width W (<= 510;
+// a strip of W columns is one workgroup of strip_waves(W) wavefronts):
 // per instance, rows are split into ceil(ny / H) chunks of balanced height;
 // columns into ceil(nx / W) strips, either of balanced width (W not a
 // multiple of 16) or starting at multiples of W (W a multiple of 16), so
@@ -305,6 +306,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.nrows = L.nrows;
     std::vector<int4> strips = make_strips(params, n_inst, ctx->chunk, ctx->width);
     d.nstrips = (int)strips.size();
+    d.nw = strip_waves(ctx->width);
 
     hipStream_t st = ctx->stream;
     auto bail = [&](hipError_t e, const char *what) {
@@ -567,6 +569,7 @@ static int set_strips(lbm_ctx *ctx, int rows, int cols)
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->dev.nstrips = (int)strips.size();
+    ctx->dev.nw = strip_waves(cols);
     ctx->chunk = rows;
     ctx->width = cols;
     for (int i = 0; i < 2; ++i)
@@ -588,7 +591,8 @@ int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
 {
     CTX_CHECK(ctx);
-    if (cols < MIN_WIDTH || cols > SWO) return fail(ctx, LBM_EINVAL, "cols must be in [16, 62]");
+    if (cols < MIN_WIDTH || cols > MAX_STRIP_COLS)
+        return fail(ctx, LBM_EINVAL, "cols must be in [16, 510]");
     return set_strips(ctx, ctx->chunk, cols);
 }
 

@@ -24,7 +24,12 @@ struct Dev {
     double *part;   // [nrows][NQR]
     double *res;    // [ninst][NRES]
     int ninst, ntiles, nrows, nstrips;
+    int nw;         // wavefronts per strip of the fused step (1, 2, 4 or 8)
 };
+
+// wavefronts per strip for a strip of `cols` output columns
+constexpr int strip_waves(int cols) { return cols <= 62 ? 1 : cols <= 126 ? 2 : cols <= 254 ? 4 : 8; }
+constexpr int MAX_STRIP_COLS = 8 * 64 - 2;
 
 hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
 hipError_t launch_step(const Dev &d, int par, hipStream_t st);

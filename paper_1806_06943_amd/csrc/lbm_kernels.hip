@@ -83,36 +83,68 @@ __device__ __forceinline__ float from_right(float v)
         __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-// One wavefront advances a strip of wo <= 62 output columns [X0, X0 + wo) and
-// ho output rows [Y0, Y0 + ho) by one time step.  Lane l owns lattice column
-// X0 - 1 + l; lanes 0 and wo + 1 are the one-column halo whose collision the
-// neighbouring strips also compute.  The wavefront marches down the rows:
-//   * an LDS ring holds rho and psi of rows c-2 .. c+2 (columns X0-3 .. X0+64)
-//     for the force stencil of collided row c;
+// Density ring of a strip of NW wavefronts: RR rows (a rolling window over
+// lattice rows) of 64 NW + 4 columns, column j holding lattice column
+// X0 - 1 - HALO + j.
+template <int NW>
+struct RingW {
+    static constexpr int W = 64 * NW + 2 * HALO;
+    float rho[2][RR][W];
+    float psi[2][RR][W];
+    float dev[2][RR][W];  // density deviations (own-node term of the collision)
+};
+
+// accessor into the ring: slot[dy + 2] is the ring row of lattice row c + dy,
+// cx the ring column of the node
+template <class RT>
+struct RingAccW {
+    const RT &R;
+    const int *slot;
+    int cx;
+    __device__ float psi(int k, int dx, int dy) const { return R.psi[k][slot[dy + HALO]][cx + dx]; }
+    __device__ float rho(int k, int dx, int dy) const { return R.rho[k][slot[dy + HALO]][cx + dx]; }
+};
+
+// One workgroup of NW wavefronts advances a strip of wo <= 64 NW - 2 output
+// columns [X0, X0 + wo) and ho output rows [Y0, Y0 + ho) by one time step.
+// Thread L owns lattice column X0 - 1 + L; threads 0 and wo + 1 are the
+// one-column halo whose collision the neighbouring strips also compute.  The
+// workgroup marches down the rows:
+//   * an LDS ring holds rho and psi of rows c-2 .. c+2 (columns X0-3 ..
+//     X0+64NW) for the force stencil of collided row c;
 //   * collided rows c-2 (upward populations) and c-1 (all) stay in registers;
 //   * output row o = c - 1 pulls f_i(x, o) = f*_i(x - e_i) from rows o-1, o,
-//     o+1, the x shift by one lane done with DPP lane shifts, bounce-back
-//     from the node itself next to a wall;
-//   * f(t+1) and rho(t+1) of the output row are written aligned.
-// The loop body has no lane-divergent branches: every lane loads a valid
-// column (idle lanes a neighbour's), rows beyond a wall read a clamped row
-// whose values are not used, and lanes that must not write give an offset
-// beyond the buffer, which the descriptor's range check drops (buffers stay
-// below 2 GiB, so that offset plus any segment offset cannot wrap into
-// range).  Memory waits are then exact.  The next row's populations are
-// loaded while the current row is collided.
+//     o+1: the x shift by one column is a DPP lane shift inside a wavefront
+//     and, across the boundary between two wavefronts, an exchange of the
+//     six edge values per component through LDS; bounce-back takes the
+//     node's own reflected population next to a wall;
+//   * f(t+1) and rho(t+1) of the output row are written.
+// The loop body has no lane-divergent branches on global memory: every lane
+// loads a valid column (idle lanes a neighbour's), rows beyond a wall read a
+// clamped row whose values are not used, and lanes that must not write give
+// an offset beyond the buffer, which the descriptor's range check drops
+// (buffers stay below 2 GiB, so that offset plus any segment offset cannot
+// wrap into range).  Memory waits are then exact.  The next row's
+// populations are loaded while the current row is collided.  Two barriers
+// per row: after the collision (the ring row of c - 2 and the edge values
+// are then free / published) and after the ring update.
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
-__global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ insts,
-                                                    const int4 *__restrict__ strips, int par)
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restrict__ insts,
+                                                         const int4 *__restrict__ strips, int par)
 {
-    __shared__ Ring R;
+    constexpr int NL = 64 * NW;
+    __shared__ RingW<NW> R;
+    // edge values of each wavefront for its neighbours: [wave][side][6]
+    __shared__ float edge[NW][2][6];
     const int4 t = strips[blockIdx.x];
     const KInst &G = insts[t.x];
     // arithmetic parameters copied once: the buffer stores below could
     // otherwise alias them
     const KPar P = kpar(G);
     const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = t.w >> 16;
-    const int l = (int)threadIdx.x;
+    const int L = (int)threadIdx.x;
+    const int l = L & 63, wv = L >> 6;
     const int nx = G.nx, ny = G.ny, walls = G.walls;
     const uint32_t qb = (uint32_t)G.pitch * 4u;   // bytes per row segment
     const uint32_t frowb = 18u * qb;              // bytes per population row
@@ -121,15 +153,15 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
     const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(G.rho[par], (uint32_t)ny * rrowb);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(G.rho[par ^ 1], (uint32_t)ny * rrowb);
-    const uint32_t xcb = (uint32_t)wrapi(X0 - 1 + l, nx) * 4u;  // collided column, bytes
-    const bool outl = (l >= 1) && (l <= wo);
+    const uint32_t xcb = (uint32_t)wrapi(X0 - 1 + L, nx) * 4u;  // collided column, bytes
+    const bool outl = (L >= 1) && (L <= wo);
     constexpr uint32_t DROP = 0x80000000u;  // out-of-range offset: store dropped
-    // ring column j holds lattice column X0 - 1 - HALO + j; lane l fills
-    // j = l (both components) and one (extra column, component) pair: lanes
+    // ring column j holds lattice column X0 - 1 - HALO + j; thread L fills
+    // j = L (both components) and one (extra column, component) pair: lanes
     // with the same pair load the same value and write it to the same place
-    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + l, nx) * 4u;
+    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 4u;
     const int xe = l & 3, ke = (l >> 2) & 1;
-    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + SW + xe, nx) * 4u + (ke ? qb : 0u);
+    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 4u + (ke ? qb : 0u);
     // per-lane parameters of the extra column's component, selected once (a
     // lane-dependent index into the parameter copy would put it in scratch)
     const float ref_e = ke ? P.rho_ref[1] : P.rho_ref[0];
@@ -153,7 +185,7 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
             q.i = (q.i + 1 == ny) ? 0 : q.i + 1;
     };
     struct RingVals {
-        float a, b, e;  // density deviations of A, B at column l; extra-column value
+        float a, b, e;  // density deviations of A, B at column L; extra-column value
     };
     // rows beyond a wall read row 0 (valid memory); ring_store replaces the values
     auto ring_load = [&](int ri) {
@@ -168,16 +200,16 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
         const bool wall = ri < 0;
         const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + v.a;
         const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + v.b;
-        R.rho[0][slot][l] = ra;
-        R.rho[1][slot][l] = rb;
-        R.psi[0][slot][l] = wall ? P.psi_wall[0] : psi_of(P, ra);
-        R.psi[1][slot][l] = wall ? P.psi_wall[1] : psi_of(P, rb);
-        R.dev[0][slot][l] = v.a;
-        R.dev[1][slot][l] = v.b;
+        R.rho[0][slot][L] = ra;
+        R.rho[1][slot][L] = rb;
+        R.psi[0][slot][L] = wall ? P.psi_wall[0] : psi_of(P, ra);
+        R.psi[1][slot][L] = wall ? P.psi_wall[1] : psi_of(P, rb);
+        R.dev[0][slot][L] = v.a;
+        R.dev[1][slot][L] = v.b;
         const float re = wall ? rwall_e : ref_e + v.e;
-        R.dev[ke][slot][SW + xe] = v.e;
-        R.rho[ke][slot][SW + xe] = re;
-        R.psi[ke][slot][SW + xe] = wall ? pwall_e : psi_of(P, re);
+        R.dev[ke][slot][NL + xe] = v.e;
+        R.rho[ke][slot][NL + xe] = re;
+        R.psi[ke][slot][NL + xe] = wall ? pwall_e : psi_of(P, re);
     };
     auto load_f = [&](int ri, float f[2][9]) {
         const uint32_t off = (uint32_t)(ri < 0 ? 0 : ri) * frowb + xcb;
@@ -229,12 +261,12 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
         float S[2][9];
         {
             float F[2][2];
-            stencil_force(P, RingAcc{R, slot, l + HALO}, F);
+            stencil_force(P, RingAccW<RingW<NW>>{R, slot, L + HALO}, F);
             float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                drho[k] = R.dev[k][slot[HALO]][l + HALO];
-                rho[k] = R.rho[k][slot[HALO]][l + HALO];
+                drho[k] = R.dev[k][slot[HALO]][L + HALO];
+                rho[k] = R.rho[k][slot[HALO]][L + HALO];
                 float mx, my;
                 mom9(f[k], mx, my);
                 jx[k] = fmaf(0.5f, F[k][0], mx);
@@ -247,6 +279,35 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
                 collide(P, k, f[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
         }
 
+        // the values that cross a wavefront boundary in the x shift: lane 63
+        // publishes the right-moving ones (1, 5, 8) for the next wavefront's
+        // lane 0, lane 0 the left-moving ones (3, 6, 7) for the previous
+        // wavefront's lane 63
+        if constexpr (NW > 1) {
+            if (l == 63) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    edge[wv][1][3 * k + 0] = Sprev[k][1];
+                    edge[wv][1][3 * k + 1] = Uprev[k][1];
+                    edge[wv][1][3 * k + 2] = S[k][8];
+                }
+            }
+            if (l == 0) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    edge[wv][0][3 * k + 0] = Sprev[k][3];
+                    edge[wv][0][3 * k + 1] = Uprev[k][2];
+                    edge[wv][0][3 * k + 2] = S[k][7];
+                }
+            }
+        }
+        // every collision of row c is done: the ring row of c - 2 is free and
+        // the edge values are visible
+        __syncthreads();
+        const int wl = wv > 0 ? wv - 1 : 0, wr = wv < NW - 1 ? wv + 1 : NW - 1;
+        const bool takel = NW > 1 && l == 0 && wv > 0;
+        const bool taker = NW > 1 && l == 63 && wv < NW - 1;
+
         // stream into output row o = c - 1; the first two iterations have no
         // output row yet and write nothing
         {
@@ -254,25 +315,31 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
             const bool wlo = walls && o == 0;
             const bool whi = walls && o == ny - 1;
             const uint32_t off =
-                (outl && it >= 2) ? (uint32_t)o * frowb + (uint32_t)(X0 - 1 + l) * 4u : DROP;
+                (outl && it >= 2) ? (uint32_t)o * frowb + (uint32_t)(X0 - 1 + L) * 4u : DROP;
             const uint32_t roff =
-                (outl && it >= 2) ? (uint32_t)o * rrowb + (uint32_t)(X0 - 1 + l) * 4u : DROP;
+                (outl && it >= 2) ? (uint32_t)o * rrowb + (uint32_t)(X0 - 1 + L) * 4u : DROP;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 float g[9];
+                float l1 = from_left(Sprev[k][1]), l5 = from_left(Uprev[k][1]), l8 = from_left(S[k][8]);
+                float r3 = from_right(Sprev[k][3]), r6 = from_right(Uprev[k][2]), r7 = from_right(S[k][7]);
+                if constexpr (NW > 1) {
+                    l1 = takel ? edge[wl][1][3 * k + 0] : l1;
+                    l5 = takel ? edge[wl][1][3 * k + 1] : l5;
+                    l8 = takel ? edge[wl][1][3 * k + 2] : l8;
+                    r3 = taker ? edge[wr][0][3 * k + 0] : r3;
+                    r6 = taker ? edge[wr][0][3 * k + 1] : r6;
+                    r7 = taker ? edge[wr][0][3 * k + 2] : r7;
+                }
                 g[0] = Sprev[k][0];
-                g[1] = from_left(Sprev[k][1]);
-                g[3] = from_right(Sprev[k][3]);
-                const float u5 = from_left(Uprev[k][1]);
-                const float u6 = from_right(Uprev[k][2]);
-                const float d7 = from_right(S[k][7]);
-                const float d8 = from_left(S[k][8]);
+                g[1] = l1;
+                g[3] = r3;
                 g[2] = wlo ? Sprev[k][4] : Uprev[k][0];
-                g[5] = wlo ? Sprev[k][7] : u5;
-                g[6] = wlo ? Sprev[k][8] : u6;
+                g[5] = wlo ? Sprev[k][7] : l5;
+                g[6] = wlo ? Sprev[k][8] : r6;
                 g[4] = whi ? Sprev[k][2] : S[k][4];
-                g[7] = whi ? Sprev[k][5] : d7;
-                g[8] = whi ? Sprev[k][6] : d8;
+                g[7] = whi ? Sprev[k][5] : r7;
+                g[8] = whi ? Sprev[k][6] : l8;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) bstore(g[i], fout, off, (uint32_t)(k * 9 + i) * qb);
                 bstore(sum9(g), rout, roff, (uint32_t)k * qb);
@@ -293,9 +360,8 @@ __global__ __launch_bounds__(SW) void k_fused_step(const KInst *__restrict__ ins
 #pragma unroll
             for (int d = 0; d < RR - 1; ++d) slot[d] = slot[d + 1];
             slot[RR - 1] = freed;
-            __syncthreads();  // every lane has read the ring row about to be replaced
             ring_store(freed, rnext, vnext);
-            __syncthreads();
+            __syncthreads();  // the new ring row and the consumed edges before reuse
             advance(cr);
         }
         advance(cc);
@@ -785,7 +851,13 @@ hipError_t launch_density(const Dev &d, int par, hipStream_t st)
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)
 {
-    k_fused_step<<<d.nstrips, SW, 0, st>>>(d.insts, d.strips, par);
+    switch (d.nw) {
+    case 1: k_fused_step<1><<<d.nstrips, 64, 0, st>>>(d.insts, d.strips, par); break;
+    case 2: k_fused_step<2><<<d.nstrips, 128, 0, st>>>(d.insts, d.strips, par); break;
+    case 4: k_fused_step<4><<<d.nstrips, 256, 0, st>>>(d.insts, d.strips, par); break;
+    case 8: k_fused_step<8><<<d.nstrips, 512, 0, st>>>(d.insts, d.strips, par); break;
+    default: return hipErrorInvalidValue;
+    }
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -5,8 +5,9 @@ event-timed kernel profile (lbm_profile_step), applies the fastest with
 lbm_set_strip_width / lbm_set_tiling and caches the choice in a JSON file
 keyed by lattice shapes, instance count and GPU architecture.  Every strip
 shape gives bitwise identical results, so tuning never changes the
-simulation.  Widths: 62 (balanced strips, fewest waves) and 48 (strips at
-multiples of 48 columns: output rows start on 64-byte boundaries).
+simulation.  Widths cover strips of 1, 2, 4 and 8 wavefronts, each either
+balanced (64 n - 2 columns) or placed at multiples of a multiple of 16
+columns (output rows start on 64-byte boundaries).
 """
 from __future__ import annotations
 
@@ -16,7 +17,9 @@ import os
 from . import lbm
 
 CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
-WIDTHS = (62, 48)
+# (output columns per strip): one wavefront per strip, balanced / aligned,
+# then strips of 2, 4 and 8 wavefronts, balanced / aligned
+WIDTHS = (62, 48, 126, 112, 254, 240, 510, 496)
 CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
                                                         "lbm_tiling.json"))
 

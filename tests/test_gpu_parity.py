@@ -7,6 +7,7 @@ literal couplings); other cases carry the bound derived for them in the
 design notes.  Integer-like results (batched vs single runs, graph vs
 launch-by-launch, repeated runs) must be bitwise equal.
 """
+import dataclasses
 import math
 import random
 from fractions import Fraction as Fr
@@ -281,3 +282,29 @@ def test_strip_height_does_not_change_results(torch):
         if ref is None:
             ref = f
         assert np.array_equal(f, ref), h
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(200, 96, 1), (600, 40, 0), (37, 21, 1)])
+def test_strip_width_does_not_change_results(torch, nx, ny, walls):
+    """Strips of 1 to 8 wavefronts, balanced or 64-byte aligned: bitwise equal results
+    (wider lattices than one strip exercise the exchange between wavefronts)."""
+    say("strip widths", nx, ny, walls)
+    if walls and ny >= 60:
+        w = W.emulsion(nx=nx, ny=ny, ndrop=3, radius=6, gx=1e-5)
+    else:
+        w = W.droplet(nx=nx, ny=ny, radius=min(nx, ny) / 4)
+        if walls:
+            w = dataclasses.replace(w, walls=1, rho_wall=(0.03, 1.0), g=((1e-5, 0.0), (1e-5, 0.0)))
+    ref = None
+    for cols, h in ((62, 16), (48, 8), (126, 12), (112, 5), (254, 16), (240, 33), (510, 7), (496, 16),
+                    (16, 4)):
+        sim = lbm.Sim([lbm.workload_instance(w)])
+        lbm.lbm_set_strip_width(sim.ctx, cols)
+        lbm.lbm_set_tiling(sim.ctx, h)
+        assert lbm.lbm_get_strip_width(sim.ctx) == cols
+        sim.step(23)
+        f = sim.populations().cpu().numpy()
+        sim.close()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), (cols, h)
