@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~15 s)")
     ap.add_argument("--chunk", type=int, default=0, help="strip height (0: autotune)")
     ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 62)")
+    ap.add_argument("--balance", type=int, default=0, help="with --width: workgroups per CU")
     ap.add_argument("--batched-steps", type=int, default=1000, help="0 skips the batched form")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint form")
     ap.add_argument("--adjoint-window", type=int, default=200)
@@ -135,7 +136,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     ms_fwd = timed(torch, fwd.stream, lambda: fwd.step(steps))
     fwd.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
-    tune.apply(prob.sim, tuning["width"], tuning["best"])
+    tune.apply(prob.sim, tuning["width"], tuning["best"], tuning.get("balance", 0))
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -160,7 +161,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     return {"workload": f"{w.nx}x{w.ny} periodic, 16 droplets R=20, g_x=1e-6, "
                         "couplings (3.0, -7.4, 6.4), tau (1.0, 0.6)",
             "steps": steps, "window": window, "objective": "J_dp (smooth pressure jump)",
-            "strip_shape": [tuning["width"], tuning["best"]],
+            "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance")},
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),
             "J": J, "grad_theta": {n: float(v) for n, v in zip(lbm.THETA_NAMES, g)},
@@ -206,9 +207,9 @@ def main():
     N = w.nx * w.ny
 
     # strip height: autotuned (untimed) unless given
-    if a.chunk > 0:
-        tune.apply(sim, a.width or 62, a.chunk)
-        tuning = {"best": a.chunk, "width": a.width or 62}
+    if a.chunk > 0 or a.balance > 0:
+        tune.apply(sim, a.width or 62, a.chunk, a.balance)
+        tuning = {"best": a.chunk, "width": a.width or 62, "balance": a.balance}
     else:
         tuning = tune.tune(sim, use_cache=False)
 

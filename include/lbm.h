@@ -153,10 +153,11 @@ int lbm_copy_probe(lbm_ctx *ctx, void *dst_dev, const void *src_dev, uint64_t nb
 int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, const char **names,
                      int32_t *n_kernels);
 
-/* Strip height of the fused step (lattice rows one wavefront advances per
- * step, default 16, at least 4).  Any value gives the same results bit for
- * bit; it trades halo recomputation against parallelism.  Synchronises the
- * stream and discards captured graphs. */
+/* Strip height of the fused step (lattice rows one strip advances per step,
+ * default 16, at least 4); selects the uniform plan (every column strip cut
+ * into ceil(ny / chunk_rows) chunks, one workgroup each).  Any value gives
+ * the same results bit for bit; it trades halo recomputation against
+ * parallelism.  Synchronises the stream and discards captured graphs. */
 int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows);
 int32_t lbm_get_tiling(const lbm_ctx *ctx);
 
@@ -169,6 +170,15 @@ int32_t lbm_get_tiling(const lbm_ctx *ctx);
  * discards captured graphs. */
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols);
 int32_t lbm_get_strip_width(const lbm_ctx *ctx);
+
+/* Balanced plan (wgs_per_cu in [1, 8]): the fused step runs as exactly
+ * wgs_per_cu workgroups per compute unit, each advancing an equal share of
+ * all strip rows (a share may cover two or more column strips), so no
+ * compute unit holds more work than another.  0 returns to the uniform plan
+ * of lbm_set_tiling.  Results are bitwise identical for every plan.
+ * Synchronises the stream and discards captured graphs. */
+int lbm_set_balance(lbm_ctx *ctx, int32_t wgs_per_cu);
+int32_t lbm_get_balance(const lbm_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Reverse-mode adjoint (gradients of objectives with respect to the state and

@@ -57,47 +57,128 @@ struct Layout {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Strips of the fused step for strip height H and output width W (<= 510;
-// a strip of W columns is one workgroup of strip_waves(W) wavefronts):
-// per instance, rows are split into ceil(ny / H) chunks of balanced height;
-// columns into ceil(nx / W) strips, either of balanced width (W not a
-// multiple of 16) or starting at multiples of W (W a multiple of 16), so
-// that every output row segment starts on a 64-byte boundary (the writes of
-// neighbouring strips then never share a 64-byte block).  The table is then
-// ordered so that consecutive workgroup indices, which the hardware deals
-// round-robin to the eight XCDs, give each XCD a contiguous run of
-// neighbouring strips (shared halo columns and rows stay in that XCD's L2).
-std::vector<int4> make_strips(const lbm_params *p, int n, int H, int W)
+// Work of the fused step: segments {inst, X0, Y0, wo | ho << 16} and, per
+// workgroup g, the range first[g] .. first[g+1]-1 of segments it advances.
+struct StripPlan {
+    std::vector<int4> segs;
+    std::vector<int> first;
+};
+
+// Column strips of an instance for output width W (<= 510; a strip of W
+// columns is one workgroup of strip_waves(W) wavefronts): ceil(nx / W)
+// strips, either of balanced width (W not a multiple of 16) or starting at
+// multiples of W (W a multiple of 16), so that every output row segment
+// starts on a 64-byte boundary (the writes of neighbouring strips then never
+// share a 64-byte block).  Returns {x0, width} pairs.
+std::vector<int2> column_strips(int nx, int W)
 {
-    std::vector<int4> tab;
+    std::vector<int2> out;
+    const int ns = ceil_div(nx, W);
     const bool aligned = W % 16 == 0;
-    for (int i = 0; i < n; ++i) {
-        const int ns = ceil_div(p[i].nx, W), nc = ceil_div(p[i].ny, H);
-        for (int c = 0; c < nc; ++c) {
-            const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
-            for (int sx = 0; sx < ns; ++sx) {
-                const int x0 = aligned ? W * sx : (int)((int64_t)p[i].nx * sx / ns);
-                const int x1 = aligned ? std::min(p[i].nx, W * (sx + 1))
-                                       : (int)((int64_t)p[i].nx * (sx + 1) / ns);
-                tab.push_back(make_int4(i, x0, y0, (x1 - x0) | ((y1 - y0) << 16)));
-            }
-        }
+    for (int sx = 0; sx < ns; ++sx) {
+        const int x0 = aligned ? W * sx : (int)((int64_t)nx * sx / ns);
+        const int x1 = aligned ? std::min(nx, W * (sx + 1)) : (int)((int64_t)nx * (sx + 1) / ns);
+        out.push_back(make_int2(x0, x1 - x0));
     }
-    constexpr int NXCD = 8;
-    const int T = (int)tab.size(), q = ceil_div(T, NXCD);
-    std::vector<int4> out;
-    out.reserve(T);
-    for (int m = 0; m < q; ++m)
-        for (int j = 0; j < NXCD; ++j)
-            if (j * q + m < T && m < q) out.push_back(tab[j * q + m]);
     return out;
 }
 
+constexpr int NXCD = 8;  // XCDs of the chip; workgroup g is dealt to XCD g % 8
+
+// Uniform plan: rows split into ceil(ny / H) chunks of balanced height, one
+// segment per workgroup.  The segments are ordered so that consecutive
+// workgroup indices, which the hardware deals round-robin to the eight
+// XCDs, give each XCD a contiguous run of neighbouring strips (shared halo
+// columns and rows stay in that XCD's L2).
+StripPlan plan_uniform(const lbm_params *p, int n, int H, int W)
+{
+    std::vector<int4> tab;
+    for (int i = 0; i < n; ++i) {
+        const std::vector<int2> cols = column_strips(p[i].nx, W);
+        const int nc = ceil_div(p[i].ny, H);
+        for (int c = 0; c < nc; ++c) {
+            const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
+            for (const int2 &cs : cols) tab.push_back(make_int4(i, cs.x, y0, cs.y | ((y1 - y0) << 16)));
+        }
+    }
+    const int T = (int)tab.size(), q = ceil_div(T, NXCD);
+    StripPlan P;
+    P.segs.reserve(T);
+    for (int m = 0; m < q; ++m)
+        for (int j = 0; j < NXCD; ++j)
+            if (j * q + m < T) P.segs.push_back(tab[j * q + m]);
+    for (int g = 0; g <= (int)P.segs.size(); ++g) P.first.push_back(g);
+    return P;
+}
+
+// Balanced plan for G workgroups: every strip-row costs the same (one row
+// of one workgroup), so each workgroup gets an equal share of all
+// strip-rows, as runs of rows in one column strip (a share that crosses the
+// end of a column becomes two or more segments).  The strip-rows are listed
+// by horizontal band (eight bands of rows per instance), then instance,
+// column and row; workgroup g takes share (g % 8) G/8 + g / 8, so each XCD
+// advances one band: vertically neighbouring shares and the strips beside
+// them meet in the same L2.
+StripPlan plan_balanced(const lbm_params *p, int n, int W, int G)
+{
+    struct Unit {
+        int inst, x0, wo, y0, y1;
+    };
+    std::vector<Unit> units;
+    int64_t T = 0;
+    for (int b = 0; b < NXCD; ++b)
+        for (int i = 0; i < n; ++i) {
+            const int y0 = (int)((int64_t)p[i].ny * b / NXCD), y1 = (int)((int64_t)p[i].ny * (b + 1) / NXCD);
+            if (y1 <= y0) continue;
+            for (const int2 &cs : column_strips(p[i].nx, W)) {
+                units.push_back({i, cs.x, cs.y, y0, y1});
+                T += y1 - y0;
+            }
+        }
+    if (G > T) G = (int)T;
+    if (G < 1) G = 1;
+    // shares of logical index l: rows [T l / G, T (l + 1) / G) of the list
+    std::vector<std::vector<int4>> share(G);
+    size_t u = 0;
+    int64_t ubase = 0;  // strip-rows before unit u
+    for (int l = 0; l < G; ++l) {
+        int64_t a = T * l / G;
+        const int64_t b = T * (l + 1) / G;
+        while (a < b) {
+            while (ubase + (units[u].y1 - units[u].y0) <= a) {
+                ubase += units[u].y1 - units[u].y0;
+                ++u;
+            }
+            const Unit &U = units[u];
+            const int64_t uend = ubase + (U.y1 - U.y0);
+            const int64_t e = std::min(b, uend);
+            const int ys = U.y0 + (int)(a - ubase), ho = (int)(e - a);
+            share[l].push_back(make_int4(U.inst, U.x0, ys, U.wo | (ho << 16)));
+            a = e;
+        }
+    }
+    StripPlan P;
+    const bool xcd = G % NXCD == 0;
+    for (int g = 0; g < G; ++g) {
+        const int l = xcd ? (g % NXCD) * (G / NXCD) + g / NXCD : g;
+        P.first.push_back((int)P.segs.size());
+        for (const int4 &sgm : share[l]) P.segs.push_back(sgm);
+    }
+    P.first.push_back((int)P.segs.size());
+    return P;
+}
+
+// segments a plan may need: uniform plans of any allowed width and height,
+// balanced plans of up to MAX_WG workgroups
+constexpr int MAX_WG = 8192;
 int max_strips(const lbm_params *p, int n)
 {
-    int t = 0;
-    for (int i = 0; i < n; ++i) t += ceil_div(p[i].nx, MIN_WIDTH) * ceil_div(p[i].ny, MIN_CHUNK);
-    return t;
+    int t = 0, cols = 0;
+    for (int i = 0; i < n; ++i) {
+        t += ceil_div(p[i].nx, MIN_WIDTH) * ceil_div(p[i].ny, MIN_CHUNK);
+        cols += ceil_div(p[i].nx, MIN_WIDTH);
+    }
+    return std::max(t, MAX_WG + NXCD * cols);
 }
 
 Layout make_layout(const lbm_params *p, int n)
@@ -111,7 +192,7 @@ Layout make_layout(const lbm_params *p, int n)
     uint64_t o = 0;
     L.off_insts = o; o = align_up(o + sizeof(KInst) * n, ALIGN);
     L.off_tiles = o; o = align_up(o + sizeof(int4) * L.ntiles, ALIGN);
-    L.off_strips = o; o = align_up(o + sizeof(int4) * L.max_strips, ALIGN);
+    L.off_strips = o; o = align_up(o + (sizeof(int4) + sizeof(int)) * L.max_strips + sizeof(int), ALIGN);
     L.off_rows = o;  o = align_up(o + sizeof(int2) * L.nrows, ALIGN);
     L.off_row0s = o; o = align_up(o + sizeof(int) * n, ALIGN);
     L.off_rho0p = o; o = align_up(o + sizeof(double *) * n, ALIGN);
@@ -212,6 +293,8 @@ struct lbm_ctx {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int chunk = DEFAULT_CHUNK;
     int width = DEFAULT_WIDTH;
+    int balance = 0;   // workgroups per CU of a balanced plan (0: uniform chunks)
+    int ncu = 256;     // compute units of the device
     std::string err;
 };
 
@@ -301,11 +384,21 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.part = (double *)(ctx->ws + L.off_part);
     d.res = (double *)(ctx->ws + L.off_res);
     d.strips = (int4 *)(ctx->ws + L.off_strips);
+    d.first = (int *)(d.strips + L.max_strips);
     d.ninst = n_inst;
     d.ntiles = L.ntiles;
     d.nrows = L.nrows;
-    std::vector<int4> strips = make_strips(params, n_inst, ctx->chunk, ctx->width);
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            ctx->ncu = ncu;
+    }
+    StripPlan plan = plan_uniform(params, n_inst, ctx->chunk, ctx->width);
+    const std::vector<int4> &strips = plan.segs;
     d.nstrips = (int)strips.size();
+    d.nwg = (int)plan.first.size() - 1;
     d.nw = strip_waves(ctx->width);
 
     hipStream_t st = ctx->stream;
@@ -324,6 +417,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     if ((e = hipMemcpyAsync(d.strips, strips.data(), sizeof(int4) * strips.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e, "copy strip table");
+    if ((e = hipMemcpyAsync(d.first, plan.first.data(), sizeof(int) * plan.first.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return bail(e, "copy workgroup table");
     if ((e = hipMemcpyAsync(d.rows, rows.data(), sizeof(int2) * rows.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
         return bail(e, "copy row table");
@@ -560,18 +656,25 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     return rc;
 }
 
-static int set_strips(lbm_ctx *ctx, int rows, int cols)
+static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance)
 {
-    std::vector<int4> strips = make_strips(ctx->params.data(), ctx->n_inst, rows, cols);
-    if ((int)strips.size() > ctx->layout.max_strips) return fail(ctx, LBM_EINVAL, "strip table overflow");
-    // the table is read by kernels already queued: order the copy after them
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, strips.data(), sizeof(int4) * strips.size(),
+    StripPlan plan = balance > 0
+                         ? plan_balanced(ctx->params.data(), ctx->n_inst, cols, balance * ctx->ncu)
+                         : plan_uniform(ctx->params.data(), ctx->n_inst, rows, cols);
+    if ((int)plan.segs.size() > ctx->layout.max_strips)
+        return fail(ctx, LBM_EINVAL, "strip table overflow");
+    // the tables are read by kernels already queued: order the copies after them
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, plan.segs.data(), sizeof(int4) * plan.segs.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.first, plan.first.data(), sizeof(int) * plan.first.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    ctx->dev.nstrips = (int)strips.size();
+    ctx->dev.nstrips = (int)plan.segs.size();
+    ctx->dev.nwg = (int)plan.first.size() - 1;
     ctx->dev.nw = strip_waves(cols);
     ctx->chunk = rows;
     ctx->width = cols;
+    ctx->balance = balance;
     for (int i = 0; i < 2; ++i)
         if (ctx->graph[i]) {
             (void)hipGraphExecDestroy(ctx->graph[i]);
@@ -585,7 +688,7 @@ int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
     CTX_CHECK(ctx);
     if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
         return fail(ctx, LBM_EINVAL, "chunk_rows must be in [4, 65535]");
-    return set_strips(ctx, chunk_rows, ctx->width);
+    return set_strips(ctx, chunk_rows, ctx->width, 0);
 }
 
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
@@ -593,10 +696,20 @@ int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
     CTX_CHECK(ctx);
     if (cols < MIN_WIDTH || cols > MAX_STRIP_COLS)
         return fail(ctx, LBM_EINVAL, "cols must be in [16, 510]");
-    return set_strips(ctx, ctx->chunk, cols);
+    return set_strips(ctx, ctx->chunk, cols, ctx->balance);
 }
 
 int32_t lbm_get_strip_width(const lbm_ctx *ctx) { return ctx ? ctx->width : -1; }
+
+int lbm_set_balance(lbm_ctx *ctx, int32_t wgs_per_cu)
+{
+    CTX_CHECK(ctx);
+    if (wgs_per_cu < 0 || wgs_per_cu > 8 || wgs_per_cu * ctx->ncu > MAX_WG)
+        return fail(ctx, LBM_EINVAL, "wgs_per_cu must be in [0, 8]");
+    return set_strips(ctx, ctx->chunk, ctx->width, wgs_per_cu);
+}
+
+int32_t lbm_get_balance(const lbm_ctx *ctx) { return ctx ? ctx->balance : -1; }
 
 int32_t lbm_get_tiling(const lbm_ctx *ctx) { return ctx ? ctx->chunk : -1; }
 

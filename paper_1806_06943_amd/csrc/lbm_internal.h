@@ -18,13 +18,15 @@ enum ResSlot {
 struct Dev {
     KInst *insts;   // [ninst]
     int4 *tiles;    // [ntiles] {inst, x0, y0, 0}: 2-D tiles of the auxiliary kernels
-    int4 *strips;   // [nstrips] {inst, X0, Y0, wo | ho << 16}: work of the fused step
+    int4 *strips;   // [nstrips] {inst, X0, Y0, wo | ho << 16}: segments of the fused step
+    int *first;     // [nwg + 1] workgroup g advances segments first[g] .. first[g+1]-1
     int2 *rows;     // [nrows]  {inst, y}
     int *row0s;     // [ninst]  first row index of each instance in rows
     double *part;   // [nrows][NQR]
     double *res;    // [ninst][NRES]
     int ninst, ntiles, nrows, nstrips;
     int nw;         // wavefronts per strip of the fused step (1, 2, 4 or 8)
+    int nwg;        // workgroups of the fused step
 };
 
 // wavefronts per strip for a strip of `cols` output columns

@@ -105,8 +105,9 @@ struct RingAccW {
     __device__ float rho(int k, int dx, int dy) const { return R.rho[k][slot[dy + HALO]][cx + dx]; }
 };
 
-// One workgroup of NW wavefronts advances a strip of wo <= 64 NW - 2 output
-// columns [X0, X0 + wo) and ho output rows [Y0, Y0 + ho) by one time step.
+// One workgroup of NW wavefronts advances its segments, one after the
+// other, by one time step; a segment is a strip of wo <= 64 NW - 2 output
+// columns [X0, X0 + wo) and ho output rows [Y0, Y0 + ho).
 // Thread L owns lattice column X0 - 1 + L; threads 0 and wo + 1 are the
 // one-column halo whose collision the neighbouring strips also compute.  The
 // workgroup marches down the rows:
@@ -131,13 +132,18 @@ struct RingAccW {
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
 template <int NW>
 __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restrict__ insts,
-                                                         const int4 *__restrict__ strips, int par)
+                                                         const int4 *__restrict__ segs,
+                                                         const int *__restrict__ first, int par)
 {
     constexpr int NL = 64 * NW;
     __shared__ RingW<NW> R;
     // edge values of each wavefront for its neighbours: [wave][side][6]
     __shared__ float edge[NW][2][6];
-    const int4 t = strips[blockIdx.x];
+    // the workgroup's segments, one after the other (a segment ends with a
+    // barrier after which no thread reads the ring or the edges again)
+    const int sg_end = first[blockIdx.x + 1];
+    for (int sg = first[blockIdx.x]; sg < sg_end; ++sg) {
+    const int4 t = segs[sg];
     const KInst &G = insts[t.x];
     // arithmetic parameters copied once: the buffer stores below could
     // otherwise alias them
@@ -366,6 +372,7 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
         }
         advance(cc);
     }
+    }  // segments
 }
 
 // ------------------------------------------------------------------ fields
@@ -852,10 +859,10 @@ hipError_t launch_density(const Dev &d, int par, hipStream_t st)
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)
 {
     switch (d.nw) {
-    case 1: k_fused_step<1><<<d.nstrips, 64, 0, st>>>(d.insts, d.strips, par); break;
-    case 2: k_fused_step<2><<<d.nstrips, 128, 0, st>>>(d.insts, d.strips, par); break;
-    case 4: k_fused_step<4><<<d.nstrips, 256, 0, st>>>(d.insts, d.strips, par); break;
-    case 8: k_fused_step<8><<<d.nstrips, 512, 0, st>>>(d.insts, d.strips, par); break;
+    case 1: k_fused_step<1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
+    case 2: k_fused_step<2><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
+    case 4: k_fused_step<4><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
+    case 8: k_fused_step<8><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
     default: return hipErrorInvalidValue;
     }
     LAUNCH_CHECK();

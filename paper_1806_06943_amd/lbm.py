@@ -100,6 +100,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_get_tiling.argtypes = [vp]
         L.lbm_get_tiling.restype = ctypes.c_int32
         L.lbm_set_strip_width.argtypes = [vp, ctypes.c_int32]
+        L.lbm_set_balance.argtypes = [vp, ctypes.c_int32]
+        L.lbm_get_balance.argtypes = [vp]
+        L.lbm_get_balance.restype = ctypes.c_int32
         L.lbm_get_strip_width.argtypes = [vp]
         L.lbm_get_strip_width.restype = ctypes.c_int32
         L.lbm_adjoint_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
@@ -230,6 +233,14 @@ def lbm_set_strip_width(ctx, cols: int):
 
 def lbm_get_strip_width(ctx) -> int:
     return int(lib().lbm_get_strip_width(ctx))
+
+
+def lbm_set_balance(ctx, wgs_per_cu: int):
+    _check(lib().lbm_set_balance(ctx, int(wgs_per_cu)), ctx)
+
+
+def lbm_get_balance(ctx) -> int:
+    return int(lib().lbm_get_balance(ctx))
 
 
 def lbm_adjoint_step(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr: int,

@@ -7,7 +7,9 @@ keyed by lattice shapes, instance count and GPU architecture.  Every strip
 shape gives bitwise identical results, so tuning never changes the
 simulation.  Widths cover strips of 1, 2, 4 and 8 wavefronts, each either
 balanced (64 n - 2 columns) or placed at multiples of a multiple of 16
-columns (output rows start on 64-byte boundaries).
+columns (output rows start on 64-byte boundaries); for each width the
+uniform plans (chunks of a candidate height) and the balanced plans (1 to 4
+workgroups per compute unit, equal shares of rows) are timed.
 """
 from __future__ import annotations
 
@@ -37,13 +39,21 @@ def _arch(sim) -> str:
         return "unknown"
 
 
-def apply(sim, width: int, height: int):
+BALANCES = (1, 2, 3, 4)
+
+
+def apply(sim, width: int, height: int, balance: int = 0):
+    """Strip width, then either uniform chunks of `height` rows or, if balance > 0,
+    the balanced plan with `balance` workgroups per compute unit."""
     lbm.lbm_set_strip_width(sim.ctx, int(width))
-    lbm.lbm_set_tiling(sim.ctx, int(height))
+    if balance > 0:
+        lbm.lbm_set_balance(sim.ctx, int(balance))
+    else:
+        lbm.lbm_set_tiling(sim.ctx, int(height))
 
 
 def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
-         widths=WIDTHS) -> dict:
+         widths=WIDTHS, balances=BALANCES) -> dict:
     """Pick the fastest strip shape for sim's context; returns the timings."""
     arch = _arch(sim)
     key = _key(sim, arch)
@@ -54,18 +64,24 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
                 cache = json.load(fh)
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache and "width" in cache[key]:
-        apply(sim, cache[key]["width"], cache[key]["best"])
-        return cache[key]
+    if use_cache and key in cache and "balance" in cache[key]:
+        e = cache[key]
+        apply(sim, e["width"], e["best"], e["balance"])
+        return e
     times = {}
     for wdt in widths:
         for h in candidates:
             apply(sim, wdt, h)
             lbm.lbm_profile_step(sim.ctx, 3)  # warm-up
-            times[(wdt, h)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
-    bw, bh = min(times, key=times.get)
-    apply(sim, bw, bh)
-    entry = {"best": bh, "width": bw, "ms": {f"{w}x{h}": v for (w, h), v in times.items()}}
+            times[(wdt, h, 0)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+        for b in balances:
+            apply(sim, wdt, 0, b)
+            lbm.lbm_profile_step(sim.ctx, 3)
+            times[(wdt, 0, b)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+    bw, bh, bb = min(times, key=times.get)
+    apply(sim, bw, bh, bb)
+    entry = {"best": bh, "width": bw, "balance": bb,
+             "ms": {(f"{w}x{h}" if b == 0 else f"{w}xbal{b}"): v for (w, h, b), v in times.items()}}
     if use_cache:
         cache[key] = entry
         try:

@@ -286,8 +286,9 @@ def test_strip_height_does_not_change_results(torch):
 
 @pytest.mark.parametrize("nx,ny,walls", [(200, 96, 1), (600, 40, 0), (37, 21, 1)])
 def test_strip_width_does_not_change_results(torch, nx, ny, walls):
-    """Strips of 1 to 8 wavefronts, balanced or 64-byte aligned: bitwise equal results
-    (wider lattices than one strip exercise the exchange between wavefronts)."""
+    """Strips of 1 to 8 wavefronts, balanced or 64-byte aligned, uniform chunks or an
+    equal share of rows per workgroup: bitwise equal results (wider lattices than one
+    strip exercise the exchange between wavefronts)."""
     say("strip widths", nx, ny, walls)
     if walls and ny >= 60:
         w = W.emulsion(nx=nx, ny=ny, ndrop=3, radius=6, gx=1e-5)
@@ -296,11 +297,16 @@ def test_strip_width_does_not_change_results(torch, nx, ny, walls):
         if walls:
             w = dataclasses.replace(w, walls=1, rho_wall=(0.03, 1.0), g=((1e-5, 0.0), (1e-5, 0.0)))
     ref = None
+    # (cols, rows or -balance): uniform plans, then balanced plans (1-4 workgroups per CU)
     for cols, h in ((62, 16), (48, 8), (126, 12), (112, 5), (254, 16), (240, 33), (510, 7), (496, 16),
-                    (16, 4)):
+                    (16, 4), (240, -2), (62, -1), (510, -3), (48, -4), (126, -2)):
         sim = lbm.Sim([lbm.workload_instance(w)])
         lbm.lbm_set_strip_width(sim.ctx, cols)
-        lbm.lbm_set_tiling(sim.ctx, h)
+        if h > 0:
+            lbm.lbm_set_tiling(sim.ctx, h)
+        else:
+            lbm.lbm_set_balance(sim.ctx, -h)
+            assert lbm.lbm_get_balance(sim.ctx) == -h
         assert lbm.lbm_get_strip_width(sim.ctx) == cols
         sim.step(23)
         f = sim.populations().cpu().numpy()
@@ -308,3 +314,21 @@ def test_strip_width_does_not_change_results(torch, nx, ny, walls):
         if ref is None:
             ref = f
         assert np.array_equal(f, ref), (cols, h)
+
+
+def test_batched_balanced_plan_equals_uniform(torch):
+    """The 96-instance mix under a balanced plan (shares spanning instances) equals the
+    uniform plan bit for bit."""
+    say("batched balanced plan")
+    ws = W.batched()[:24]
+    outs = []
+    for bal in (0, 2):
+        sim = lbm.Sim([lbm.workload_instance(w) for w in ws])
+        lbm.lbm_set_strip_width(sim.ctx, 62)
+        if bal:
+            lbm.lbm_set_balance(sim.ctx, bal)
+        sim.step(17)
+        outs.append([sim.populations(i).cpu().numpy() for i in (0, 5, 23)])
+        sim.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
