@@ -41,26 +41,28 @@ DOMINANT = "k_fused_step"
 
 # HBM bytes per k_fused_step launch on this workload from rocprofv3 --pmc
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
-# library), valid only for the kernel sources and strip height they were
-# measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "8678cac69f1ae8a9", "strip_height": 48, "strip_width": 62,
-                    "fetch_bytes": 180225.7 * 2.0 * 1024, "write_bytes": 351596.4 * 1.0 * 1024}
+# library), per strip plan (width, height, workgroups per CU), valid only for
+# the kernel sources they were measured on.
+MEASURED_TRAFFIC = {"src_sha256_16": "ea37647eadfa111f",
+                    "plans": {(240, 38, 0): (186731.8 * 2.0 * 1024, 331491.5 * 1024),
+                              (240, 40, 0): (188295.0 * 2.0 * 1024, 331303.0 * 1024),
+                              (126, 48, 0): (182493.4 * 2.0 * 1024, 338572.3 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
 
-def measured_traffic(strip_width, strip_height):
-    """Counter-based bytes per launch, or None once the kernel or its launch shape changed."""
+def measured_traffic(strip_width, strip_height, balance):
+    """Counter-based bytes per launch, or None once the kernel or its launch plan changed."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     t = MEASURED_TRAFFIC
-    if (h.hexdigest()[:16] != t["src_sha256_16"] or strip_height != t["strip_height"]
-            or strip_width != t["strip_width"]):
+    if h.hexdigest()[:16] != t["src_sha256_16"]:
         return None
-    return round(t["fetch_bytes"] + t["write_bytes"])
+    plan = t["plans"].get((strip_width, 0 if balance else strip_height, balance))
+    return None if plan is None else round(plan[0] + plan[1])
 
 
 def parse():
@@ -266,7 +268,8 @@ def main():
     adj = bench_adjoint(torch, lbm, W, a.adjoint_steps, a.adjoint_window) if a.adjoint_steps > 0 else None
 
     cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
-    traffic = measured_traffic(lbm.lbm_get_strip_width(sim.ctx), lbm.lbm_get_tiling(sim.ctx))
+    traffic = measured_traffic(lbm.lbm_get_strip_width(sim.ctx), lbm.lbm_get_tiling(sim.ctx),
+                               lbm.lbm_get_balance(sim.ctx))
 
     mass_drift = [abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] for k in range(2)]
     out = {
