@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from paper_1806_06943_amd import lbm
+from paper_1806_06943_amd import lbm, tune
 from paper_1806_06943_amd import workloads as W
 from tests.exact_forces import forces_exact
 
@@ -224,11 +224,15 @@ def test_batched_instances_equal_single_runs(torch):
 
 # ---------------------------------------------------------------- full size, sampled
 def test_spinodal_full_size_sampled_nodes(torch):
-    """2048x2048 spinodal workload in the benchmark's launch configuration: sampled nodes
-    of step t+1 against the oracle's single-node step of the GPU state at t; FP64 mass."""
+    """2048x2048 spinodal workload in the benchmark's launch configuration (the tuned
+    strip plan): sampled nodes of step t+1 against the oracle's single-node step of the
+    GPU state at t; FP64 mass."""
     w = W.spinodal()
     say("spinodal 2048^2")
     sim = lbm.Sim([lbm.workload_instance(w)])
+    tune.tune(sim, use_cache=False, nrep=5)
+    say("plan", lbm.lbm_get_strip_width(sim.ctx),
+        lbm.lbm_get_tiling(sim.ctx), lbm.lbm_get_balance(sim.ctx))
     obs0, _ = sim.observables()
     sim.step(64)
     f = sim.populations_full()
@@ -245,6 +249,64 @@ def test_spinodal_full_size_sampled_nodes(torch):
     obs1, _ = sim.observables()
     for k in range(2):
         assert abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] < 1e-6
+
+
+@pytest.mark.parametrize("ratio", [0.5, 4.0])
+def test_emulsion_full_size_sampled_nodes(torch, ratio):
+    """4096x512 walled emulsion (200 droplets, g_x = 1e-6, nu_A/nu_B = ratio) under the
+    tuned strip plan: sampled nodes, wall rows and lattice edges included, of step t+1
+    against the oracle's single-node step; FP64 mass of each component."""
+    w = W.emulsion(tau_ratio=ratio)
+    say("emulsion 4096x512 ratio", ratio)
+    sim = lbm.Sim([lbm.workload_instance(w)])
+    tune.tune(sim, use_cache=False, nrep=5)
+    obs0, _ = sim.observables()
+    sim.step(48)
+    f = sim.populations_full()
+    sim.step(1)
+    f1 = sim.populations_full()
+    p = oparams(w)
+    r = np.random.default_rng(11)
+    nodes = [(0, 0), (4095, 511), (0, 511), (4095, 0), (2048, 1), (17, 510)] + \
+            [(int(r.integers(0, 4096)), int(y)) for y in r.integers(0, 512, size=30)] + \
+            [(int(r.integers(0, 4096)), y) for y in (0, 1, 510, 511) for _ in range(3)]
+    for x, y in nodes:
+        want = O.step_at(p, f, x, y)
+        assert np.abs(f1[:, :, y, x] - want).max() < 2e-7, (x, y)
+    sim.step(151)
+    obs1, _ = sim.observables()
+    for k in range(2):
+        assert abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] < 1e-6
+
+
+def test_batched_workload_per_instance_laplace(torch):
+    """The 96-instance droplet batch in one context under its tuned plan, 300 steps: one
+    instance of each size against a full oracle run (fields, and the Laplace pressure
+    jump of Sec. III B by the same protocol)."""
+    ws = W.batched()
+    say("batched 96 instances")
+    sim = lbm.Sim([lbm.workload_instance(w) for w in ws])
+    tune.tune(sim, use_cache=False, nrep=5)
+    steps = 300
+    sim.step(steps)
+    obs, _ = sim.observables()
+    seen = set()
+    for i, w in enumerate(ws):
+        if w.nx in seen:
+            continue
+        seen.add(w.nx)
+        say("instance", i, w.nx, w.tau, w.G2)
+        rho, u = sim.fields(i)
+        p = oparams(w)
+        fo = O.run(p, O.init(p, w.rhoA, w.rhoB), steps)
+        flo = O.fields(p, fo)
+        er = [rel(rho.cpu().numpy()[k], flo["rho"][k]) for k in range(2)]
+        eu = [rel(u.cpu().numpy()[d], flo["u"][d]) for d in range(2)]
+        assert max(er) <= 1e-5 and max(eu) <= 5e-5, (i, er, eu)
+        L = O.laplace(p, flo)
+        assert abs(obs[i]["dp"] - L["dp"]) <= 1e-3 * abs(L["dp"]), (i, obs[i]["dp"], L["dp"])
+        assert abs(obs[i]["R_eff"] - L["R"]) <= 1e-4 * L["R"]
+    assert len(seen) == 4
 
 
 # ---------------------------------------------------------------- geometry edge cases
