@@ -180,6 +180,9 @@ int32_t lbm_get_strip_width(const lbm_ctx *ctx);
 int lbm_set_balance(lbm_ctx *ctx, int32_t wgs_per_cu);
 int32_t lbm_get_balance(const lbm_ctx *ctx);
 
+/* Workgroups of one launch of the fused step under the current strip plan. */
+int32_t lbm_get_workgroups(const lbm_ctx *ctx);
+
 /* ------------------------------------------------------------------------
  * Reverse-mode adjoint (gradients of objectives with respect to the state and
  * to theta = (G1, G2, G_AB, tau_A, tau_B), where G1 and G2 move the couplings

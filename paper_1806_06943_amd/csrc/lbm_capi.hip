@@ -711,6 +711,8 @@ int lbm_set_balance(lbm_ctx *ctx, int32_t wgs_per_cu)
 
 int32_t lbm_get_balance(const lbm_ctx *ctx) { return ctx ? ctx->balance : -1; }
 
+int32_t lbm_get_workgroups(const lbm_ctx *ctx) { return ctx ? ctx->dev.nwg : -1; }
+
 int32_t lbm_get_tiling(const lbm_ctx *ctx) { return ctx ? ctx->chunk : -1; }
 
 int lbm_destroy(lbm_ctx *ctx)

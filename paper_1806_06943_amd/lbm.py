@@ -103,6 +103,8 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_balance.argtypes = [vp, ctypes.c_int32]
         L.lbm_get_balance.argtypes = [vp]
         L.lbm_get_balance.restype = ctypes.c_int32
+        L.lbm_get_workgroups.argtypes = [vp]
+        L.lbm_get_workgroups.restype = ctypes.c_int32
         L.lbm_get_strip_width.argtypes = [vp]
         L.lbm_get_strip_width.restype = ctypes.c_int32
         L.lbm_adjoint_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp]
@@ -241,6 +243,10 @@ def lbm_set_balance(ctx, wgs_per_cu: int):
 
 def lbm_get_balance(ctx) -> int:
     return int(lib().lbm_get_balance(ctx))
+
+
+def lbm_get_workgroups(ctx) -> int:
+    return int(lib().lbm_get_workgroups(ctx))
 
 
 def lbm_adjoint_step(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr: int,

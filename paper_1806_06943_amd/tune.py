@@ -91,3 +91,37 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
         except OSError:
             pass
     return entry
+
+
+def _main():
+    """Print the fused step's time for every strip plan of a sweep (one GPU)."""
+    import argparse
+    from . import workloads as W
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--workload", default="spinodal", choices=("spinodal", "emulsion", "batched"))
+    ap.add_argument("--widths", default="240,496,126,62,48")
+    ap.add_argument("--heights", default="8:72:2", help="start:stop:step")
+    ap.add_argument("--balances", default="1,2,3,4")
+    ap.add_argument("--nrep", type=int, default=30)
+    a = ap.parse_args()
+    ws = W.batched() if a.workload == "batched" else [getattr(W, a.workload)()]
+    sim = lbm.Sim([lbm.workload_instance(w) for w in ws])
+    h0, h1, hs = (int(v) for v in a.heights.split(":"))
+    rows = []
+    for wdt in (int(v) for v in a.widths.split(",")):
+        plans = [(h, 0) for h in range(h0, h1, hs)] + [(0, int(b)) for b in a.balances.split(",") if b]
+        for h, b in plans:
+            apply(sim, wdt, h, b)
+            lbm.lbm_profile_step(sim.ctx, 3)
+            ms = dict(lbm.lbm_profile_step(sim.ctx, a.nrep))["k_fused_step"]
+            rows.append((ms, wdt, h, b))
+            print(f"width {wdt:4d} {'balance ' + str(b) if b else 'height ' + str(h):>10s}  "
+                  f"workgroups {lbm.lbm_get_workgroups(sim.ctx):6d}  "
+                  f"{ms:.5f} ms", flush=True)
+    rows.sort()
+    print("best:", ", ".join(f"{w}x{('bal' + str(b)) if b else h} {ms:.5f} ms" for ms, w, h, b in rows[:8]))
+    sim.close()
+
+
+if __name__ == "__main__":
+    _main()
