@@ -233,13 +233,15 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
         // invariant), and FP32 arithmetic there would leave a noise floor on
         // small gradients.  Only the stored lam is rounded to FP32.
         using R = double;
-        R lpart[2][9];
         R Fb[2][2];
         R gtau[2] = {0.0, 0.0};
+        // the local part of lam is lam_c[k] + lam_a[k] a_i + mb[k] . e_i (MODE 0:
+        // lam_a = 1 - 1/tau_k; MODE 1: lam_a = 0, a = 0)
+        R lam_c[2] = {0.0, 0.0}, lam_a[2] = {0.0, 0.0}, mbx[2] = {0.0, 0.0}, mby[2] = {0.0, 0.0};
+        float a[2][9];
         const R Ux = ux, Uy = uy, UU = (R)ux * ux + (R)uy * uy, ID = (R)1 / ((R)rho[0] * A.it[0] + (R)rho[1] * A.it[1]);
         if (MODE == 0) {
             // transpose of streaming (pull of the downstream adjoint)
-            R a[2][9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const int yd = y + c_ey[i];
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                     const R eu = ex * Ux + ey * Uy;
                     const R eF = ex * Fx + ey * Fy;
                     const R Em1 = 3.0 * eu + 4.5 * eu * eu - 1.5 * UU;  // E - 1
-                    const R ai = a[k][i];
+                    const R ai = (R)a[k][i];
                     rb += ai * w * (1.0 + Em1);
                     const R awr = ai * w * rk * it;
                     ubx += awr * (3.0 * ex + 9.0 * eu * ex - 3.0 * Ux);
@@ -284,7 +286,6 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                 gtau[k] = (gt + 0.5 * gg) * it * it;
             }
             // transpose of Eq. 3 and of Eq. 6 (j = m + F/2)
-            R mbx[2], mby[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const R it = A.it[k];
@@ -295,13 +296,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                 mby[k] = jby;
                 Fb[k][0] += 0.5 * jbx;
                 Fb[k][1] += 0.5 * jby;
+                lam_c[k] = rbar[k];
+                lam_a[k] = 1.0 - it;
             }
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int i = 0; i < 9; ++i)
-                    lpart[k][i] = (1.0 - (R)A.it[k]) * a[k][i] + mbx[k] * (R)c_ex[i] +
-                                  mby[k] * (R)c_ey[i] + rbar[k];
         } else {
             // J_Q: u_x = (sum_k m_kx + F_kx / 2) / rho, summed over x and / nx
             const R rt = (R)rho[0] + rho[1];
@@ -310,10 +307,13 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
             acc[5] = ubar * (R)A.qscale;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) lpart[k][i] = (R)A.qscale * ((R)c_ex[i] - ubar) * irt;
+                // q (e_x - u_x) / rho
+                lam_c[k] = -(R)A.qscale * ubar * irt;
+                mbx[k] = (R)A.qscale * irt;
                 Fb[k][0] = 0.5 * (R)A.qscale * irt;
                 Fb[k][1] = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) a[k][i] = 0.0f;
             }
         }
         // own-node terms of the force transpose and the coupling gradients
@@ -326,7 +326,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
             const R rown = psibar * (R)expf(-rho[k] * A.inv_rho0) - (R)A.gab * srF +
                            (R)A.g[k][0] * Fb[k][0] + (R)A.g[k][1] * Fb[k][1];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) lam[xidx(A, k * 9 + i, x, y)] = (float)(lpart[k][i] + rown);
+            for (int i = 0; i < 9; ++i)
+                lam[xidx(A, k * 9 + i, x, y)] =
+                    (float)((lam_a[k] * (R)a[k][i] + mbx[k] * (R)c_ex[i] + mby[k] * (R)c_ey[i] + lam_c[k]) + rown);
             A.scr[sidx(A, SCR_FBAR + 2 * k, x, y)] = (float)Fb[k][0];
             A.scr[sidx(A, SCR_FBAR + 2 * k + 1, x, y)] = (float)Fb[k][1];
             acc[0] += -(R)psi[k] * s1F;

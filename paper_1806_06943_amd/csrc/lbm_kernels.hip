@@ -809,7 +809,9 @@ __global__ __launch_bounds__(RT) void k_red_final3(const KInst *__restrict__ ins
 
 // ------------------------------------------------------------------ copy probe
 // each thread moves CPT 16-byte vectors, all loads issued before the stores
-constexpr int CPT = 4;
+// (one per thread in 256-thread blocks was the fastest shape measured on
+// MI355X, ahead of 4 or 8 per thread and of grid-stride loops)
+constexpr int CPT = 1;
 __global__ __launch_bounds__(256) void k_copy(float4 *__restrict__ dst,
                                               const float4 *__restrict__ src, int64_t n4)
 {
