@@ -13,6 +13,8 @@
  *   common velocity      u^eq = sum_k j_k/tau_k / sum_k rho_k/tau_k     (Eq. 3)
  *   collision            BGK per component towards f^eq(rho_k, u^eq)
  *                        plus the Guo forcing term                     (Eqs. 1, 2, 5)
+ *   (or, with the velocity-shift forcing of the original model: j_k without
+ *   F_k/2 and BGK towards f^eq(rho_k, u^eq + tau_k F_k / rho_k), Sec. II A)
  *   streaming            periodic in x; periodic in y, or half-way
  *                        bounce-back walls half a link outside rows 0
  *                        and ny-1                                      (Eq. 1, Sec. III A)
@@ -50,12 +52,19 @@ extern "C" {
 
 typedef struct lbm_ctx lbm_ctx;
 
+#define LBM_FORCING_GUO 0
+#define LBM_FORCING_SHIFT 1
+
 /* Model parameters of one lattice instance, as the paper states the model. */
 typedef struct {
     int32_t nx, ny;      /* lattice size, each >= 1 (small tori alias the 5x5 stencil)   */
     int32_t walls;       /* 0: periodic x and y; 1: periodic x, walls below row 0 and
                             above row ny-1 (half-way bounce-back, Sec. III A)            */
-    int32_t reserved;    /* must be 0                                                    */
+    int32_t forcing;     /* LBM_FORCING_GUO (0): the present model's forcing term with the
+                            common velocity (Eq. 5); LBM_FORCING_SHIFT (1): the velocity
+                            shift of the original two-range model (its explicit form C^SC,
+                            Sec. II A), for comparison.  All instances of a context use
+                            the same scheme.                                            */
     double G_AB;         /* inter-species coupling of Eq. 9 (> 0 repulsive)             */
     double G1[2];        /* short-range coupling of Eq. 8 per component {A, B}          */
     double G2[2];        /* mid-range coupling of Eq. 8 per component {A, B}            */
@@ -91,7 +100,8 @@ typedef struct {
  * parameters are params[0..n_inst-1].  Returns LBM_EINVAL for bad sizes. */
 int lbm_workspace_bytes(const lbm_params *params, int32_t n_inst, uint64_t *bytes);
 
-/* Create a context for n_inst >= 1 independent instances.
+/* Create a context for n_inst >= 1 independent instances (all with the same
+ * forcing scheme; LBM_EUNSUPPORTED otherwise).
  *   params     host array [n_inst], copied
  *   rhoA0/B0   host FP64 initial densities, instance after instance, each
  *              row-major ny*nx; the initial state is equilibrium at rest
@@ -210,7 +220,8 @@ int32_t lbm_get_workgroups(const lbm_ctx *ctx);
  * grad_dev[0..4] += (d f(t+1) / d theta)^T lam_in_dev (device FP64, may be
  * NULL to skip the gradient).  lam_out_dev must not overlap f_dev or
  * lam_in_dev.  Asynchronous on the context's stream; consecutive calls on
- * one context are ordered by the stream. */
+ * one context are ordered by the stream.  The adjoint entry points return
+ * LBM_EUNSUPPORTED for the velocity-shift forcing. */
 int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
                      float *lam_out_dev, double *grad_dev);
 

@@ -20,6 +20,11 @@
  * gives identical results):
  *   0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)
  *
+ * Forcing: the present model's Guo term with the common velocity (Eq. 5,
+ * forcing = 0), or, for comparison, the velocity shift of the original
+ * two-range model in its explicit form C^SC (Sec. II A, forcing = 1; the
+ * common velocity then averages the bare population momenta).
+ *
  * Readings of points the paper leaves open (each is listed with its reason
  * in the design notes of the repository):
  *   - equilibrium carries the usual factor 1/2 on the quadratic term
@@ -54,6 +59,9 @@ typedef struct {
     double rho0;        /* pseudopotential reference density (Sec. II B)  */
     double g[2][2];     /* body acceleration per component, (x, y)        */
     double rho_wall[2]; /* virtual densities beyond the walls             */
+    int forcing;        /* 0: Guo term with the common velocity (Eq. 5);
+                           1: velocity shift of the original model (the
+                           explicit form C^SC of Sec. II A)              */
 } ora_params;
 
 /* number of OpenMP threads the row loops use (1 without OpenMP) */
@@ -287,7 +295,10 @@ void ora_guo(double tau, double ux, double uy, double Fx, double Fy, double *out
     for (int i = 0; i < 9; ++i) out9[i] = guo_i(i, tau, ux, uy, Fx, Fy);
 }
 
-/* ---- Eqs. 6 and 3: moments with F/2 and the common velocity at a node ---- */
+/* ---- Eqs. 6 and 3: moments with F/2 and the common velocity at a node ----
+ * jx, jy carry F/2 (Eq. 6) for the observables in either scheme; the common
+ * velocity (Eq. 3) averages the component momenta of the scheme: with F/2
+ * for the Guo term, the bare population momenta for the velocity shift. */
 typedef struct {
     double rho[2], jx[2], jy[2], Fx[2], Fy[2], ux, uy;
 } node_macro;
@@ -307,12 +318,24 @@ static void macro_at(const ora_params *p, const double *f, const dens_src *rho, 
         force_at(p, rho, k, x, y, &m->Fx[k], &m->Fy[k]);
         m->jx[k] = mx + 0.5 * m->Fx[k];
         m->jy[k] = my + 0.5 * m->Fy[k];
-        numx += m->jx[k] / p->tau[k];
-        numy += m->jy[k] / p->tau[k];
+        numx += (p->forcing ? mx : m->jx[k]) / p->tau[k];
+        numy += (p->forcing ? my : m->jy[k]) / p->tau[k];
         den += m->rho[k] / p->tau[k];
     }
     m->ux = numx / den;
     m->uy = numy / den;
+}
+
+/* ---- velocity-shift forcing term of the original model (Sec. II A) ----
+ * C^SC = [f^eq(rho, u + F tau / rho) - f^eq(rho, u)] / tau */
+static double shift_i(int i, double tau, double rho, double ux, double uy, double Fx, double Fy)
+{
+    return (feq_i(i, rho, ux + Fx * tau / rho, uy + Fy * tau / rho) - feq_i(i, rho, ux, uy)) / tau;
+}
+
+void ora_shift(double tau, double rho, double ux, double uy, double Fx, double Fy, double *out9)
+{
+    for (int i = 0; i < 9; ++i) out9[i] = shift_i(i, tau, rho, ux, uy, Fx, Fy);
 }
 
 /* ---- Eq. 1 right-hand side: post-collision value of f_{k,i} at a node ---- */
@@ -322,7 +345,8 @@ static double post_collision(const ora_params *p, const double *f, const node_ma
     double fi = f[FIDX(p, k, i, x, y)];
     double tau = p->tau[k];
     double eq = feq_i(i, m->rho[k], m->ux, m->uy);
-    double c = guo_i(i, tau, m->ux, m->uy, m->Fx[k], m->Fy[k]);
+    double c = p->forcing ? shift_i(i, tau, m->rho[k], m->ux, m->uy, m->Fx[k], m->Fy[k])
+                          : guo_i(i, tau, m->ux, m->uy, m->Fx[k], m->Fy[k]);
     return fi - (fi - eq) / tau + c;
 }
 
@@ -580,6 +604,10 @@ void ora_adjoint_step(const ora_params *p, const double *f, const double *lam_ne
                       double *grad, double *work)
 {
     size_t N = (size_t)p->nx * p->ny;
+    if (p->forcing) { /* the adjoint is written for the Guo term only */
+        for (size_t n = 0; n < 18 * N; ++n) lam[n] = NAN;
+        return;
+    }
     double *rho_arr = work, *psi = work + 2 * N, *Fbar = work + 4 * N, *rhobar = work + 8 * N;
     ora_density(p, f, rho_arr);
     psi_field(p, rho_arr, psi);

@@ -33,6 +33,7 @@ class _CParams(ctypes.Structure):
         ("G_AB", ctypes.c_double), ("G1", ctypes.c_double * 2), ("G2", ctypes.c_double * 2),
         ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
         ("g", ctypes.c_double * 4), ("rho_wall", ctypes.c_double * 2),
+        ("forcing", ctypes.c_int),
     ]
 
 
@@ -49,6 +50,7 @@ class Params:
     g: tuple = ((0.0, 0.0), (0.0, 0.0))
     walls: int = 0
     rho_wall: tuple = (0.0, 0.0)
+    forcing: int = 0   # 0: Guo term (present model), 1: velocity shift (original model)
 
     def c(self) -> _CParams:
         def pair(v):
@@ -63,6 +65,7 @@ class Params:
         gg = np.asarray(self.g, dtype=np.float64).reshape(2, 2)
         c.g[:] = [float(v) for v in gg.ravel()]
         c.rho_wall[:] = pair(self.rho_wall)
+        c.forcing = int(self.forcing)
         return c
 
 
@@ -83,6 +86,7 @@ def lib():
         L.ora_forces.argtypes = [P, _D, _D]
         L.ora_feq.argtypes = [ctypes.c_double] * 3 + [_D]
         L.ora_guo.argtypes = [ctypes.c_double] * 5 + [_D]
+        L.ora_shift.argtypes = [ctypes.c_double] * 6 + [_D]
         L.ora_step.argtypes = [P, _D, _D, _D]
         L.ora_run.argtypes = [P, _D, ctypes.c_long, _D]
         L.ora_step_at.argtypes = [P, _D, ctypes.c_int, ctypes.c_int, _D]
@@ -127,6 +131,13 @@ def feq(rho, ux, uy):
 def guo(tau, ux, uy, Fx, Fy):
     out = np.zeros(9)
     lib().ora_guo(tau, ux, uy, Fx, Fy, _ptr(out))
+    return out
+
+
+def shift(tau, rho, ux, uy, Fx, Fy):
+    """Velocity-shift forcing term C^SC of the original model (Sec. II A)."""
+    out = np.zeros(9)
+    lib().ora_shift(tau, rho, ux, uy, Fx, Fy, _ptr(out))
     return out
 
 

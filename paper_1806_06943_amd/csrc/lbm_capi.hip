@@ -227,7 +227,8 @@ std::string check_params(const lbm_params &p)
     if ((uint64_t)inst_layout(p).fsize * sizeof(float) >= ((uint64_t)1 << 31))
         return "lattice too large: a population buffer must stay below 2 GiB";
     if (p.walls != 0 && p.walls != 1) return "walls must be 0 or 1";
-    if (p.reserved != 0) return "reserved field must be 0";
+    if (p.forcing != LBM_FORCING_GUO && p.forcing != LBM_FORCING_SHIFT)
+        return "forcing must be LBM_FORCING_GUO or LBM_FORCING_SHIFT";
     const double *d = &p.G_AB;
     if (!finite_all(d, (int)((sizeof(lbm_params) - offsetof(lbm_params, G_AB)) / sizeof(double))))
         return "parameters must be finite";
@@ -348,6 +349,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     for (int i = 0; i < n_inst; ++i) {
         std::string m = check_params(params[i]);
         if (!m.empty()) return fail(nullptr, LBM_EINVAL, "instance " + std::to_string(i) + ": " + m);
+        if (params[i].forcing != params[0].forcing)
+            return fail(nullptr, LBM_EUNSUPPORTED, "all instances of a context need the same forcing");
     }
     Layout L = make_layout(params, n_inst);
     if (workspace_bytes < L.total)
@@ -400,6 +403,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.nstrips = (int)strips.size();
     d.nwg = (int)plan.first.size() - 1;
     d.nw = strip_waves(ctx->width);
+    d.forcing = params[0].forcing;
 
     hipStream_t st = ctx->stream;
     auto bail = [&](hipError_t e, const char *what) {
@@ -771,6 +775,8 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float
     CTX_CHECK(ctx);
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
+    if (ctx->params[inst].forcing != LBM_FORCING_GUO)
+        return fail(ctx, LBM_EUNSUPPORTED, "the adjoint is written for the Guo forcing");
     if (!f_dev || !lam_in_dev || !lam_out_dev) return fail(ctx, LBM_EINVAL, "null argument");
     const lbm_params &p = ctx->params[inst];
     const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
@@ -807,6 +813,8 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     CTX_CHECK(ctx);
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
+    if (ctx->params[inst].forcing != LBM_FORCING_GUO)
+        return fail(ctx, LBM_EUNSUPPORTED, "the adjoint is written for the Guo forcing");
     if (nsteps < 0 || !lam_dev || !tmp_dev || (nsteps > 0 && !f_store_dev))
         return fail(ctx, LBM_EINVAL, "bad arguments");
     const lbm_params &p = ctx->params[inst];
@@ -838,6 +846,8 @@ int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, int32_t objective, const float 
     CTX_CHECK(ctx);
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
+    if (ctx->params[inst].forcing != LBM_FORCING_GUO)
+        return fail(ctx, LBM_EUNSUPPORTED, "the adjoint is written for the Guo forcing");
     if (!f_dev || !J || !dtheta) return fail(ctx, LBM_EINVAL, "null argument");
     if (objective < LBM_OBJ_DP || objective > LBM_OBJ_MASS_A)
         return fail(ctx, LBM_EINVAL, "unknown objective");
@@ -885,6 +895,8 @@ int lbm_set_params(lbm_ctx *ctx, int32_t inst, const lbm_params *params)
     std::string m = check_params(*params);
     if (!m.empty()) return fail(ctx, LBM_EINVAL, m);
     const lbm_params &old = ctx->params[inst];
+    if (params->forcing != old.forcing)
+        return fail(ctx, LBM_EUNSUPPORTED, "the forcing scheme of a context cannot change");
     if (params->nx != old.nx || params->ny != old.ny || params->walls != old.walls ||
         (float)params->rho_ref[0] != (float)old.rho_ref[0] ||
         (float)params->rho_ref[1] != (float)old.rho_ref[1])

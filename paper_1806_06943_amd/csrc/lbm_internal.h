@@ -27,6 +27,7 @@ struct Dev {
     int ninst, ntiles, nrows, nstrips;
     int nw;         // wavefronts per strip of the fused step (1, 2, 4 or 8)
     int nwg;        // workgroups of the fused step
+    int forcing;    // 0: Guo term (Eq. 5), 1: velocity shift of the original model
 };
 
 // wavefronts per strip for a strip of `cols` output columns

@@ -129,8 +129,11 @@ struct RingAccW {
 // populations are loaded while the current row is collided.  Two barriers
 // per row: after the collision (the ring row of c - 2 and the edge values
 // are then free / published) and after the ring update.
+// FS selects the forcing: 0 the Guo term with the common velocity (Eq. 5),
+// 1 the velocity shift of the original model (momenta without F/2, BGK
+// towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
-template <int NW>
+template <int NW, int FS>
 __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restrict__ insts,
                                                          const int4 *__restrict__ segs,
                                                          const int *__restrict__ first, int par)
@@ -275,14 +278,22 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
                 rho[k] = R.rho[k][slot[HALO]][L + HALO];
                 float mx, my;
                 mom9(f[k], mx, my);
-                jx[k] = fmaf(0.5f, F[k][0], mx);
-                jy[k] = fmaf(0.5f, F[k][1], my);
+                jx[k] = FS ? mx : fmaf(0.5f, F[k][0], mx);
+                jy[k] = FS ? my : fmaf(0.5f, F[k][1], my);
             }
             float ux, uy;
             common_velocity(P, rho, jx, jy, ux, uy);
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
-                collide(P, k, f[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
+            for (int k = 0; k < 2; ++k) {
+                if constexpr (FS) {
+                    // equilibrium velocity shifted by tau_k F_k / rho_k
+                    const float s = recip(rho[k] * P.it[k]);
+                    collide(P, k, f[k], drho[k], rho[k], 0.0f, 0.0f, fmaf(F[k][0], s, ux),
+                            fmaf(F[k][1], s, uy), S[k]);
+                } else {
+                    collide(P, k, f[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
+                }
+            }
         }
 
         // the values that cross a wavefront boundary in the x shift: lane 63
@@ -860,12 +871,22 @@ hipError_t launch_density(const Dev &d, int par, hipStream_t st)
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)
 {
-    switch (d.nw) {
-    case 1: k_fused_step<1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
-    case 2: k_fused_step<2><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
-    case 4: k_fused_step<4><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
-    case 8: k_fused_step<8><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
-    default: return hipErrorInvalidValue;
+    if (d.forcing) {
+        switch (d.nw) {
+        case 1: k_fused_step<1, 1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 2: k_fused_step<2, 1><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 4: k_fused_step<4, 1><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 8: k_fused_step<8, 1><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (d.nw) {
+        case 1: k_fused_step<1, 0><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 2: k_fused_step<2, 0><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 4: k_fused_step<4, 0><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 8: k_fused_step<8, 0><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     LAUNCH_CHECK();
     return hipSuccess;

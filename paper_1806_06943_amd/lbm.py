@@ -36,7 +36,7 @@ THETA_NAMES = ("G1", "G2", "G_AB", "tau_A", "tau_B")
 class lbm_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("forcing", ctypes.c_int32),
         ("G_AB", ctypes.c_double), ("G1", ctypes.c_double * 2), ("G2", ctypes.c_double * 2),
         ("tau", ctypes.c_double * 2), ("psi_rho0", ctypes.c_double),
         ("g", (ctypes.c_double * 2) * 2), ("rho_wall", ctypes.c_double * 2),
@@ -129,12 +129,17 @@ def _check(rc: int, ctx=None):
         raise LBMError(rc, msg.decode() if msg else "")
 
 
+LBM_FORCING_GUO = 0
+LBM_FORCING_SHIFT = 1
+
+
 def make_params(nx, ny, G_AB, G1, G2, tau, g=((0.0, 0.0), (0.0, 0.0)), walls=0,
-                rho_wall=(0.0, 0.0), rho_ref=(0.0, 0.0), psi_rho0=1.0) -> lbm_params:
+                rho_wall=(0.0, 0.0), rho_ref=(0.0, 0.0), psi_rho0=1.0,
+                forcing=LBM_FORCING_GUO) -> lbm_params:
     def pair(v):
         return (float(v), float(v)) if np.isscalar(v) else (float(v[0]), float(v[1]))
     p = lbm_params()
-    p.nx, p.ny, p.walls, p.reserved = int(nx), int(ny), int(walls), 0
+    p.nx, p.ny, p.walls, p.forcing = int(nx), int(ny), int(walls), int(forcing)
     p.G_AB = float(G_AB)
     p.G1[:] = pair(G1)
     p.G2[:] = pair(G2)
@@ -300,8 +305,9 @@ class Sim:
     """One context over one or more instances, with its workspace in a torch tensor.
 
     ``instances`` is a list of dicts with keys nx, ny, rhoA, rhoB, G_AB, G1, G2,
-    tau and optionally g, walls, rho_wall, rho_ref (default: the mean initial
-    density of each component, the reference of the FP32 deviation storage).
+    tau and optionally g, walls, rho_wall, forcing, rho_ref (default: the mean
+    initial density of each component, the reference of the FP32 deviation
+    storage).
     """
 
     def __init__(self, instances, device="cuda:0", stream=None):
@@ -318,7 +324,8 @@ class Sim:
                                            g=w.get("g", ((0.0, 0.0), (0.0, 0.0))),
                                            walls=w.get("walls", 0),
                                            rho_wall=w.get("rho_wall", (0.0, 0.0)),
-                                           rho_ref=rho_ref))
+                                           rho_ref=rho_ref,
+                                           forcing=w.get("forcing", LBM_FORCING_GUO)))
             rA.append(np.asarray(w["rhoA"], dtype=np.float64).ravel())
             rB.append(np.asarray(w["rhoB"], dtype=np.float64).ravel())
         self.n_inst = len(self.params)

@@ -41,7 +41,7 @@ def test_workspace_bytes_and_validation():
             lbm.lbm_workspace_bytes([_ok_params(**bad)])
         assert ei.value.code == lbm.LBM_EINVAL
     p = _ok_params()
-    p.reserved = 7
+    p.forcing = 7
     with pytest.raises(lbm.LBMError):
         lbm.lbm_workspace_bytes([p])
 

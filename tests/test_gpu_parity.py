@@ -394,3 +394,79 @@ def test_batched_balanced_plan_equals_uniform(torch):
         sim.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- velocity-shift forcing
+def shift_instance(nx, ny, walls=0, seed=5, tau=(1.0, 0.7)):
+    w = W.droplet(nx=nx, ny=ny, radius=min(nx, ny) / 4, couplings=W.COUPLINGS_PAPER, tau=tau)
+    d = lbm.workload_instance(w)
+    d["forcing"] = lbm.LBM_FORCING_SHIFT
+    if walls:
+        d.update(walls=1, rho_wall=(0.03, 1.0), g=((1e-5, 0.0), (1e-5, 0.0)))
+    return d
+
+
+def shift_oparams(d):
+    return O.Params(nx=d["nx"], ny=d["ny"], G_AB=d["G_AB"], G1=d["G1"], G2=d["G2"], tau=d["tau"],
+                    g=d.get("g", ((0.0, 0.0), (0.0, 0.0))), walls=d.get("walls", 0),
+                    rho_wall=d.get("rho_wall", (0.0, 0.0)), forcing=1)
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_shift_forcing_single_step(torch, walls):
+    """Velocity-shift forcing of the original model: one step from a developed GPU state
+    against the oracle's step of the same state."""
+    say("shift single step", walls)
+    d = shift_instance(70, 37, walls)
+    sim = lbm.Sim([d])
+    sim.step(30)
+    f = sim.populations_full()
+    sim.step(1)
+    f1 = sim.populations_full()
+    want = O.step(shift_oparams(d), f)
+    sim.close()
+    assert np.abs(f1 - want).max() < 2e-7
+
+
+def test_shift_forcing_droplet_1000_steps(torch):
+    """(equal relaxation times: away from them this droplet diverges under the velocity
+    shift, in the oracle as well, the scheme's known instability)"""
+    say("shift droplet 1000 steps")
+    d = shift_instance(64, 64, tau=(1.0, 1.0))
+    sim = lbm.Sim([d])
+    sim.step(1000)
+    rho, u = sim.fields()
+    p = shift_oparams(d)
+    flo = O.fields(p, O.run(p, O.init(p, d["rhoA"], d["rhoB"]), 1000))
+    er = [rel(rho.cpu().numpy()[k], flo["rho"][k]) for k in range(2)]
+    eu = [rel(u.cpu().numpy()[k], flo["u"][k]) for k in range(2)]
+    say("errors", er, eu)
+    sim.close()
+    assert max(er) <= 1e-5 and max(eu) <= 5e-5, (er, eu)
+
+
+def test_shift_forcing_plans_and_adjoint_refusal(torch):
+    say("shift plans")
+    d = shift_instance(200, 40)
+    ref = None
+    for cols, h in ((62, 16), (240, 10), (112, 7), (48, -2)):
+        sim = lbm.Sim([d])
+        lbm.lbm_set_strip_width(sim.ctx, cols)
+        if h > 0:
+            lbm.lbm_set_tiling(sim.ctx, h)
+        else:
+            lbm.lbm_set_balance(sim.ctx, -h)
+        sim.step(19)
+        f = sim.populations().cpu().numpy()
+        if ref is None:
+            ref = f
+            lam = torch.zeros_like(sim.populations())
+            with pytest.raises(lbm.LBMError) as ei:
+                sim.adjoint_seed("dp", sim.populations(), lam)
+            assert ei.value.code == lbm.LBM_EUNSUPPORTED
+        sim.close()
+        assert np.array_equal(f, ref), (cols, h)
+    # one forcing per context
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.Sim([d, dict(d, forcing=lbm.LBM_FORCING_GUO)])
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
