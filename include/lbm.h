@@ -133,6 +133,22 @@ int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar);
  * Asynchronous. */
 int lbm_fields(lbm_ctx *ctx, int32_t inst, float *rho_dev, float *u_dev);
 
+/* Pressure tensor (Sec. II B) of instance inst into the device buffer
+ * P_dev[3][ny][nx] (FP32; P_xx, P_yy, P_xy): P = P^int + P^kin, with
+ *   P^int_k = 1/2 sum_e c_k(e) psi_k(x) psi_k(x+e) e e
+ *           + 1/2 G_AB sum_i w_i rho_k(x) rho_kbar(x+e_i) e_i e_i
+ *   (c_k(e) = G_{k,1} w(e) + G_{k,2} p(e)), the pair-sum form of the forces
+ *   of Eqs. 8, 9, equal to the interaction part of Eq. 11 in bulk;
+ *   P^kin = sum_{k,i} f_{k,i} e_i e_i for the Guo forcing (the static
+ *   problem), sum_k rho_k cs^2 delta + K^tau of the original model for the
+ *   velocity shift (density gradients by central differences).
+ * If line_tension is not NULL it receives (1/ny) sum_{x,y} (P_xx - P_yy)
+ * (FP64): the line tension of Eqs. 16, 17 for interfaces orthogonal to x
+ * (per interface pair it is the overall line tension gamma_f; one interface
+ * gives gamma), and the stream is synchronised; otherwise asynchronous.
+ * Overwrites the instance's field scratch. */
+int lbm_pressure(lbm_ctx *ctx, int32_t inst, float *P_dev, double *line_tension);
+
 /* Copy the populations f_{k,i}(x, t) (post-streaming, pre-collision) of
  * instance inst as FP32 deviations f - w_i rho_ref[k] into the device buffer
  * f_dev[2][9][ny][nx] (D2Q9 order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)

@@ -825,3 +825,92 @@ double ora_objective(const ora_params *p, const double *f, int which, double *la
         }
     return J;
 }
+
+/* ======================================================================
+ * Pressure tensor (Sec. II B) and the flat-interface integrals of Sec. II C.
+ *
+ * P = P^int + P^kin.  The kinetic part of the static problem is the second
+ * moment of the populations, sum_{k,i} f_{k,i} e_i e_i (present model).
+ * The interaction part is fixed by the paper only through its divergence
+ * (minus the total force); for the pairwise lattice forces of Eqs. 8 and 9
+ * the pair-sum (virial) form
+ *   P^int_k(x) = 1/2 sum_e c_k(e) psi_k(x) psi_k(x+e) e e
+ *              + 1/2 G_AB sum_i w_i rho_k(x) rho_kbar(x+e_i) e_i e_i,
+ *   c_k(e) = G_{k,1} w(e) + G_{k,2} p(e),
+ * is used: it equals the interaction part of the bulk equation of state
+ * (Eq. 11) in a uniform state, and its sum over a flat interface is the
+ * total virial of the pairs that cross it, which is what the surface-tension
+ * integral (Eq. 16) needs.  For the velocity-shift forcing the kinetic part
+ * is the paper's explicit sum_k rho_k cs^2 delta + K^tau (the tau-dependent
+ * terms), with tau = (rho_A tau_A + rho_B tau_B) / rho, F the total force
+ * and the density gradients by central differences (a reading: the paper
+ * does not state the discretisation).
+ * Output per node: P[c][y][x], c = 0: xx, 1: yy, 2: xy.
+ * ====================================================================== */
+void ora_pressure(const ora_params *p, const double *f, double *P)
+{
+    size_t N = (size_t)p->nx * p->ny;
+    double *rho_arr = (double *)malloc(2 * N * sizeof(double));
+    double *psi = (double *)malloc(2 * N * sizeof(double));
+    ora_density(p, f, rho_arr);
+    psi_field(p, rho_arr, psi);
+    dens_src rho = {rho_arr, psi, NULL};
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            size_t n = NODE(p, x, y);
+            double pxx = 0.0, pyy = 0.0, pxy = 0.0;
+            for (int k = 0; k < 2; ++k) {
+                int kb = 1 - k;
+                double ps = psi_at(p, &rho, k, x, y), rk = rho_at(p, &rho, k, x, y);
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        int e2 = dx * dx + dy * dy;
+                        if (e2 == 0) continue;
+                        double c = p->G1[k] * w_of(e2) + p->G2[k] * p_of(e2);
+                        double v = 0.5 * c * ps * psi_at(p, &rho, k, x + dx, y + dy);
+                        if (e2 <= 2)
+                            v += 0.5 * p->G_AB * w_of(e2) * rk * rho_at(p, &rho, kb, x + dx, y + dy);
+                        pxx += v * dx * dx;
+                        pyy += v * dy * dy;
+                        pxy += v * dx * dy;
+                    }
+                if (!p->forcing) {
+                    for (int i = 0; i < 9; ++i) {
+                        double fi = f[FIDX(p, k, i, x, y)];
+                        pxx += fi * EX[i] * EX[i];
+                        pyy += fi * EY[i] * EY[i];
+                        pxy += fi * EX[i] * EY[i];
+                    }
+                } else {
+                    pxx += rk * CS2;
+                    pyy += rk * CS2;
+                }
+            }
+            if (p->forcing) {
+                /* K^tau of the original model */
+                double ra = rho_arr[n], rb = rho_arr[N + n], rt = ra + rb;
+                double t = (ra * p->tau[0] + rb * p->tau[1]) / rt, t2 = (t - 0.5) * (t - 0.5);
+                double F[2] = {0.0, 0.0};
+                for (int k = 0; k < 2; ++k) {
+                    double fx, fy;
+                    force_at(p, &rho, k, x, y, &fx, &fy);
+                    F[0] += fx;
+                    F[1] += fy;
+                }
+                double g[2];
+                g[0] = (log(rho_at(p, &rho, 0, x + 1, y)) - log(rho_at(p, &rho, 0, x - 1, y))
+                        - log(rho_at(p, &rho, 1, x + 1, y)) + log(rho_at(p, &rho, 1, x - 1, y))) * 0.5;
+                g[1] = (log(rho_at(p, &rho, 0, x, y + 1)) - log(rho_at(p, &rho, 0, x, y - 1))
+                        - log(rho_at(p, &rho, 1, x, y + 1)) + log(rho_at(p, &rho, 1, x, y - 1))) * 0.5;
+                double cc = CS2 * CS2 * ra * rb / rt * t2;
+                pxx += t2 * F[0] * F[0] / rt + cc * g[0] * g[0];
+                pyy += t2 * F[1] * F[1] / rt + cc * g[1] * g[1];
+                pxy += t2 * F[0] * F[1] / rt + cc * g[0] * g[1];
+            }
+            P[n] = pxx;
+            P[N + n] = pyy;
+            P[2 * N + n] = pxy;
+        }
+    free(rho_arr);
+    free(psi);
+}

@@ -87,6 +87,7 @@ def lib():
         L.ora_feq.argtypes = [ctypes.c_double] * 3 + [_D]
         L.ora_guo.argtypes = [ctypes.c_double] * 5 + [_D]
         L.ora_shift.argtypes = [ctypes.c_double] * 6 + [_D]
+        L.ora_pressure.argtypes = [P, _D, _D]
         L.ora_step.argtypes = [P, _D, _D, _D]
         L.ora_run.argtypes = [P, _D, ctypes.c_long, _D]
         L.ora_step_at.argtypes = [P, _D, ctypes.c_int, ctypes.c_int, _D]
@@ -271,6 +272,33 @@ def value_and_grad(p: Params, f0: np.ndarray, steps: int, which: str | int):
 def objective_after(p: Params, f0: np.ndarray, steps: int, which: str | int) -> float:
     """J(f(steps)) only (for finite differences)."""
     return objective(p, run(p, f0, steps), which)[0]
+
+
+# ---------------------------------------------------------------- pressure tensor (FP64)
+def pressure(p: Params, f: np.ndarray) -> np.ndarray:
+    """P[c][y][x], c = xx, yy, xy: pair-sum interaction part plus kinetic part (Sec. II B)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    P = np.zeros((3, p.ny, p.nx))
+    c = p.c()
+    lib().ora_pressure(ctypes.byref(c), _ptr(f), _ptr(P))
+    return P
+
+
+def line_tension(P: np.ndarray) -> float:
+    """Eq. 16 / Eq. 17 for interfaces orthogonal to x: sum_x (P_xx - P_yy), mean over y."""
+    return float((P[0] - P[1]).sum(axis=1).mean())
+
+
+def disjoining_pressure(h: np.ndarray, gf: np.ndarray, gamma: float) -> np.ndarray:
+    """Eq. 19 from gamma_f(h) on a grid of h: s = gamma_f - 2 gamma,
+    Pi(h) = s(h)/h - int_h^inf s/h'^2 dh' (trapezoid rule, s beyond the last h taken as 0)."""
+    h = np.asarray(h, dtype=np.float64)
+    s = np.asarray(gf, dtype=np.float64) - 2.0 * gamma
+    g = s / h ** 2
+    tail = np.zeros_like(h)
+    for j in range(len(h) - 2, -1, -1):
+        tail[j] = tail[j + 1] + 0.5 * (g[j] + g[j + 1]) * (h[j + 1] - h[j])
+    return s / h - tail
 
 
 # ---------------------------------------------------------------- observables (numpy, FP64)

@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 TARGET = os.path.join(PKG, "liblbm_hip.so")
-SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip", "lbm_capi.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip", "lbm_pressure.hip", "lbm_capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

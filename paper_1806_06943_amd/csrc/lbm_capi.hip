@@ -788,6 +788,28 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float
     return LBM_OK;
 }
 
+int lbm_pressure(lbm_ctx *ctx, int32_t inst, float *P_dev, double *line_tension)
+{
+    CTX_CHECK(ctx);
+    int rc = check_inst(ctx, inst);
+    if (rc) return rc;
+    if (!P_dev) return fail(ctx, LBM_EINVAL, "null output");
+    const lbm_params &p = ctx->params[inst];
+    const KInst &K = ctx->hinst[inst];
+    // block partials and the final sum in the instance's field scratch
+    double *part = (double *)(K.fld + (int64_t)SCR_PART * K.plane);
+    double *res = part + adjoint_blocks(p.nx, p.ny);
+    hipError_t e = launch_pressure(ctx->dev, p, inst, ctx->par, P_dev, part, res, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "pressure kernels");
+    if (line_tension) {
+        double sum = 0.0;
+        HIP_TRY(ctx, hipMemcpyAsync(&sum, res, sizeof sum, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        *line_tension = sum / p.ny;
+    }
+    return LBM_OK;
+}
+
 int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
 {
     CTX_CHECK(ctx);

@@ -1,6 +1,7 @@
 // Host/device shared declarations of the HIP library (not part of the C-ABI).
 #pragma once
 
+#include "lbm.h"
 #include "lbm_device.h"
 
 namespace lbm {
@@ -87,6 +88,10 @@ constexpr int N_ADJ_KERNELS = 4;
 const char *adjoint_kernel_name(int j);
 hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const float *lam_next,
                                  float *lam, double *grad, hipStream_t st);
+
+// pressure tensor P[3][ny][nx] of instance inst and the FP64 sum of P_xx - P_yy
+hipError_t launch_pressure(const Dev &d, const lbm_params &p, int inst, int par, float *out,
+                           double *part, double *res, hipStream_t st);
 
 // kernels of one step, for timing: number, names, and a launcher of kernel j
 constexpr int N_STEP_KERNELS = 1;

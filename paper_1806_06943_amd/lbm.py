@@ -112,6 +112,7 @@ def lib() -> ctypes.CDLL:
                                        P(ctypes.c_double), P(ctypes.c_double)]
         L.lbm_set_params.argtypes = [vp, ctypes.c_int32, P(lbm_params)]
         L.lbm_record.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp]
+        L.lbm_pressure.argtypes = [vp, ctypes.c_int32, vp, P(ctypes.c_double)]
         L.lbm_adjoint_run.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp]
         L.lbm_profile_adjoint.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_char_p),
@@ -269,6 +270,14 @@ def lbm_adjoint_seed(ctx, inst: int, objective: int, f_ptr: int, lam_ptr: int | 
     return float(J.value), np.array(list(dth))
 
 
+def lbm_pressure(ctx, inst: int, P_ptr: int, want_line_tension: bool = True):
+    """Pressure tensor into P_ptr ([3][ny][nx] FP32); returns the line tension or None."""
+    lt = ctypes.c_double()
+    _check(lib().lbm_pressure(ctx, inst, ctypes.c_void_p(P_ptr),
+                              ctypes.byref(lt) if want_line_tension else None), ctx)
+    return float(lt.value) if want_line_tension else None
+
+
 def lbm_record(ctx, inst: int, nsteps: int, f_store_ptr: int):
     _check(lib().lbm_record(ctx, inst, int(nsteps), ctypes.c_void_p(f_store_ptr)), ctx)
 
@@ -375,6 +384,13 @@ class Sim:
         f = self.populations(inst).cpu().numpy().astype(np.float64)
         w = np.array([16, 4, 4, 4, 4, 1, 1, 1, 1], dtype=np.float64) / 36.0
         return f + w[None, :, None, None] * np.asarray(p.rho_ref[:])[:, None, None, None]
+
+    def pressure(self, inst: int = 0):
+        """(P [3, ny, nx] FP32 on the device, line tension sum (P_xx - P_yy) / ny)."""
+        p = self.params[inst]
+        P = self.torch.empty((3, p.ny, p.nx), dtype=self.torch.float32, device=self.device)
+        lt = lbm_pressure(self.ctx, inst, P.data_ptr())
+        return P, lt
 
     def populations_into(self, f_dev, inst: int = 0):
         """Export the populations into a contiguous [2, 9, ny, nx] FP32 device tensor (async)."""

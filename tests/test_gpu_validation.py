@@ -12,6 +12,10 @@
   Below M = 1/10 this droplet diverges at these couplings, in the FP64
   oracle as well.
 
+* Pressure tensor (Sec. II B): the library's tensor and line tension against
+  the oracle's; flat-interface gamma = 0.04 independent of M within 1.2 %
+  (Sec. III C); disjoining pressure (Eqs. 17-19) with the shapes of Fig. 3a.
+
 Viscosities in Eq. 19 are the bulk-phase mixture viscosities sum_k rho_k nu_k,
 as in the oracle's pin of the same flow.
 """
@@ -127,3 +131,101 @@ def test_spurious_currents_follow_the_papers_trends(torch):
     assert us[(1 / 10, -7.4)] > us[(1 / 5, -7.4)] > us[(1.0, -7.4)]
     # shrinks as G_A1 grows
     assert us[(1.0, -8.0)] > us[(1.0, -7.4)] > us[(1.0, -6.0)]
+
+
+# ---------------------------------------------------------------- pressure tensor
+def slab_instance(nx, ny, film, G1, G2, tau=(1.0, 1.0), forcing=0, film_is_B=True):
+    """Periodic in x: A everywhere except a film of B (or the reverse) of `film` columns."""
+    x = np.arange(nx)
+    inside = (x >= (nx - film) // 2) & (x < (nx - film) // 2 + film)
+    a_hi = ~inside if film_is_B else inside
+    rA = np.repeat(np.where(a_hi, 1.0, 0.03)[None, :], ny, axis=0)
+    rB = np.repeat(np.where(a_hi, 0.03, 1.0)[None, :], ny, axis=0)
+    return dict(nx=nx, ny=ny, rhoA=rA, rhoB=rB, G_AB=3.0, G1=G1, G2=G2, tau=tau, forcing=forcing)
+
+
+@pytest.mark.parametrize("case", ["droplet", "walls", "shift"])
+def test_pressure_tensor_matches_oracle(torch, case):
+    say("pressure parity", case)
+    rng = np.random.default_rng(3)
+    nx, ny = 70, 37
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    disc = (xx - 33.2) ** 2 + (yy - 17.6) ** 2 <= 100
+    d = dict(nx=nx, ny=ny, rhoA=np.where(disc, 1.0, 0.03) + 1e-3 * rng.standard_normal((ny, nx)),
+             rhoB=np.where(disc, 0.03, 1.0), G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.8))
+    if case == "walls":
+        d.update(walls=1, rho_wall=(0.03, 1.0), g=((1e-5, 0.0), (1e-5, 0.0)))
+    if case == "shift":
+        d.update(forcing=1, tau=(1.0, 1.0))
+    sim = lbm.Sim([d])
+    sim.step(40)
+    P, lt = sim.pressure()
+    torch.cuda.synchronize()
+    p = O.Params(nx=nx, ny=ny, G_AB=3.0, G1=-7.4, G2=6.4, tau=d["tau"], g=d.get("g", ((0, 0), (0, 0))),
+                 walls=d.get("walls", 0), rho_wall=d.get("rho_wall", (0.0, 0.0)),
+                 forcing=d.get("forcing", 0))
+    Po = O.pressure(p, sim.populations_full())
+    sim.close()
+    err = np.linalg.norm(P.cpu().numpy() - Po) / np.linalg.norm(Po)
+    lto = O.line_tension(Po)
+    say("P rel err", err, "line tension", lt, lto)
+    assert err < 1e-6
+    assert abs(lt - lto) <= 1e-5 * np.abs(Po[0] - Po[1]).sum() / ny
+
+
+def test_flat_interface_gamma_on_gpu(torch):
+    """gamma of flat interfaces at the emulsion couplings (0.04, Sec. III D) and its
+    independence of the viscosity ratio (within 1.2 % over M = 1/10, 1, 10, Sec. III C)."""
+    say("flat gamma")
+    # the oracle pin's slab (96 x 4, an A slab of 48 columns, 40000 steps): the bulk
+    # densities of wider periodic slabs relax by diffusion only and take far longer
+    gam = {}
+    for M in (0.1, 1.0, 10.0):
+        sim = lbm.Sim([slab_instance(96, 4, 48, -7.4, 6.4, tau=(1.0, 0.5 + 0.5 * M), film_is_B=False)])
+        sim.step(40000)
+        _, lt = sim.pressure()
+        sim.close()
+        gam[M] = lt / 2
+        say("M", M, "gamma", gam[M])
+    g1 = gam[1.0]
+    assert abs(g1 - 0.04) / 0.04 < 0.10
+    assert max(abs(v - g1) / g1 for v in gam.values()) <= 0.012, gam
+
+
+def _film_instance(nx, ny, film, G1, G2, hi, lo):
+    x = np.arange(nx)
+    inside = (x >= (nx - film) // 2) & (x < (nx - film) // 2 + film)
+    rA = np.repeat(np.where(inside, lo, hi)[None, :], ny, axis=0)
+    rB = np.repeat(np.where(inside, hi, lo)[None, :], ny, axis=0)
+    return dict(nx=nx, ny=ny, rhoA=rA, rhoB=rB, G_AB=3.0, G1=G1, G2=G2, tau=(1.0, 1.0))
+
+
+def test_disjoining_pressure_shapes_of_fig3a(torch):
+    """Eqs. 17-19 on films of B of thickness h between A (G_AB = 3.0), started at the
+    coexistence densities of a long wide-slab run: the single-range case
+    (G_A1 = G_A2 = 0) has a negative disjoining pressure at small h, the two-range
+    cases a positive peak, higher for lower G_A1 (Fig. 3a and its caption)."""
+    say("disjoining pressure")
+    hs = [2, 3, 4, 5, 6, 8, 12, 24, 48]
+    peak = {}
+    for G1, G2 in ((0.0, 0.0), (-6.0, 5.0), (-8.0, 7.0)):
+        sim = lbm.Sim([_film_instance(192, 4, 96, G1, G2, 1.0, 0.03)])
+        sim.step(200000)
+        r = sim.fields()[0].cpu().numpy()
+        sim.close()
+        hi, lo = float(r[0, 0, 0]), float(r[0, 0, 96])
+        gf = []
+        for h in hs + [128]:
+            sim = lbm.Sim([_film_instance(h + 128, 4, h, G1, G2, hi, lo)])
+            sim.step(60000)
+            _, lt = sim.pressure()
+            sim.close()
+            gf.append(lt)
+        gamma = gf.pop() / 2
+        pis = O.disjoining_pressure(np.array(hs, float), np.array(gf), gamma) * 10.0 / gamma
+        say("G", (G1, G2), "gamma", gamma, "Pi*", np.round(pis, 3).tolist())
+        small = pis[:5]  # h <= 6
+        peak[(G1, G2)] = small.max()
+        if G1 == 0.0:
+            assert small.min() < -0.3 and small.max() < 0.01, pis
+    assert peak[(-6.0, 5.0)] > 0.05 and peak[(-8.0, 7.0)] > peak[(-6.0, 5.0)], peak
