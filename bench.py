@@ -43,11 +43,11 @@ DOMINANT = "k_fused_step"
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
 # library), per strip plan (width, height, workgroups per CU), valid only for
 # the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "585e85479fbd10dc",
-                    "plans": {(240, 38, 0): (186619.1 * 2.0 * 1024, 331498.1 * 1024),
-                              (240, 40, 0): (188220.9 * 2.0 * 1024, 331280.7 * 1024),
-                              (240, 42, 0): (188797.5 * 2.0 * 1024, 330897.4 * 1024),
-                              (126, 46, 0): (180999.8 * 2.0 * 1024, 338945.8 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "af6e1f6cf4cd8324",
+                    "plans": {(240, 38, 0): (186701.5 * 2.0 * 1024, 331498.4 * 1024),
+                              (240, 40, 0): (188215.9 * 2.0 * 1024, 331286.7 * 1024),
+                              (240, 42, 0): (188843.0 * 2.0 * 1024, 330910.7 * 1024),
+                              (126, 46, 0): (181034.0 * 2.0 * 1024, 338808.4 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
