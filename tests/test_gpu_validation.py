@@ -15,6 +15,10 @@
 * Pressure tensor (Sec. II B): the library's tensor and line tension against
   the oracle's; flat-interface gamma = 0.04 independent of M within 1.2 %
   (Sec. III C); disjoining pressure (Eqs. 17-19) with the shapes of Fig. 3a.
+* Droplet collisions (Sec. III C, Figs. 5-6): two equal droplets of A in B
+  meeting head-on at Ca ~ 0.3 and We ~ 15 bounce back under the present model
+  at M = 1 and M = 3 (the film of B between them survives); the single-range
+  model coalesces in the same collision; the original model bounces at M = 1.
 
 Viscosities in Eq. 19 are the bulk-phase mixture viscosities sum_k rho_k nu_k,
 as in the oracle's pin of the same flow.
@@ -229,3 +233,90 @@ def test_disjoining_pressure_shapes_of_fig3a(torch):
         if G1 == 0.0:
             assert small.min() < -0.3 and small.max() < 0.01, pis
     assert peak[(-6.0, 5.0)] > 0.05 and peak[(-8.0, 7.0)] > peak[(-6.0, 5.0)], peak
+
+
+COLL_GAMMA = 0.043  # flat-interface gamma of the Sec. III D couplings (flat-gamma test above)
+
+
+def collide(torch, G1, G2, tau, forcing=0, U=0.12, nx=320, ny=160, R=21, relax=3000,
+            samples=16, every=500):
+    """Two droplets of radius R relaxed at rest 10 nodes apart, then given velocities
+    +-U/2 along x (equilibrium populations at the relaxed densities, the velocity
+    weighted by the local A fraction so the matrix starts at rest).  Returns the
+    droplet density and, per sample, (A regions with rho_A > 1/2, distance of the
+    two halves' A centroids, largest rho_B in the gap on the axis)."""
+    from scipy import ndimage
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    cy, c1, c2 = ny // 2, nx / 2 - R - 5, nx / 2 + R + 5
+    A = ((xx - c1) ** 2 + (yy - cy) ** 2 <= R * R) | ((xx - c2) ** 2 + (yy - cy) ** 2 <= R * R)
+    sim = lbm.Sim([dict(nx=nx, ny=ny, rhoA=np.where(A, 1.0, 0.03), rhoB=np.where(A, 0.03, 1.0),
+                        G_AB=3.0, G1=G1, G2=G2, tau=tau, forcing=forcing)])
+    try:
+        sim.step(relax)
+        rho = sim.fields()[0].cpu().numpy().astype(np.float64)
+        assert np.isfinite(rho).all()
+        rho_drop = float(rho[0, cy, int(c1)])
+        ux = np.where(xx < nx / 2, U / 2, -U / 2) * rho[0] / (rho[0] + rho[1])
+        f = np.empty((2, 9, ny, nx))
+        for k in range(2):
+            for y in range(ny):
+                for x in range(nx):
+                    f[k, :, y, x] = O.feq(rho[k, y, x], ux[y, x], 0.0)
+        w = np.array([16, 4, 4, 4, 4, 1, 1, 1, 1]) / 36.0
+        ref = np.asarray(sim.params[0].rho_ref[:])
+        dev = f - w[None, :, None, None] * ref[:, None, None, None]
+        sim.set_populations(torch.from_numpy(dev.astype(np.float32)).cuda())
+        hist = []
+        left = xx < nx / 2
+        for _ in range(samples):
+            sim.step(every)
+            rho = sim.fields()[0].cpu().numpy().astype(np.float64)
+            assert np.isfinite(rho).all()
+            _, n = ndimage.label(rho[0] > 0.5)
+            wA = rho[0] * (rho[0] > 0.5)
+            xl = (wA * xx)[left].sum() / wA[left].sum()
+            xr = (wA * xx)[~left].sum() / wA[~left].sum()
+            gap = rho[1, cy - 2:cy + 3, nx // 2 - 3:nx // 2 + 4].max()
+            hist.append((n, xr - xl, gap))
+    finally:
+        sim.close()
+    return rho_drop, hist
+
+
+@pytest.mark.parametrize("M", [1, 3])
+def test_droplet_collision_bounces_at_both_viscosity_ratios(torch, M):
+    """Present model, mu_A = 0.1 (tau_A = 0.8), mu_B = M mu_A (Figs. 5b, 6b)."""
+    say("collision present M", M)
+    tau = (0.8, 0.5 + 0.3 * M)
+    R, U = 21, 0.12
+    rho_drop, hist = collide(torch, -7.4, 6.4, tau, U=U, R=R)
+    say("rho_A", rho_drop, "samples", [(n, round(s, 1), round(g, 3)) for n, s, g in hist])
+    mu_A = rho_drop * (tau[0] - 0.5) / 3.0
+    Ca, We = mu_A * U / COLL_GAMMA, rho_drop * 2 * R * U * U / COLL_GAMMA
+    assert 0.25 < Ca < 0.35 and 12.0 < We < 18.0, (Ca, We)
+    sep = [s for _, s, _ in hist]
+    assert all(n == 2 for n, _, _ in hist), hist
+    assert all(g > 0.5 for _, _, g in hist), hist  # the film of B is never drained
+    smin = min(sep)
+    assert smin < 2 * R, sep  # the droplets met and flattened against the film
+    assert sep[-1] > smin + 10.0 and sep.index(smin) < len(sep) // 2, sep  # and bounced back
+
+
+def test_droplet_collision_coalesces_without_the_two_range_interaction(torch):
+    """Single-range model (G_A1 = G_A2 = 0), same collision: the film drains."""
+    say("collision single-range")
+    _, hist = collide(torch, 0.0, 0.0, (0.8, 0.8))
+    say("samples", [(n, round(s, 1), round(g, 3)) for n, s, g in hist])
+    n, _, gap = hist[-1]
+    assert n == 1 and gap < 0.3, hist
+
+
+def test_droplet_collision_original_model_bounces_at_unit_ratio(torch):
+    """Original model (velocity shift), M = 1 (Fig. 5a).  At mu_A = 0.1 these couplings
+    diverge under the velocity shift (the FP64 oracle as well), so tau = 1 here."""
+    say("collision original M 1")
+    _, hist = collide(torch, -7.4, 6.4, (1.0, 1.0), forcing=1)
+    say("samples", [(n, round(s, 1), round(g, 3)) for n, s, g in hist])
+    sep = [s for _, s, _ in hist]
+    assert all(n == 2 for n, _, _ in hist) and all(g > 0.5 for _, _, g in hist), hist
+    assert sep[-1] > min(sep) + 10.0, sep
