@@ -8,11 +8,15 @@
 // with those of t+1).  The collision needs exactly that
 // rounded sum, so the step reads it instead of summing again.
 //
-// Layout: row-major rows of population segments, f[y][q][x] with q = 9 k + i
-// and a row segment of `pitch` floats (x fastest), and likewise rho[y][k][x].
-// A wavefront working on one lattice row touches one contiguous block of
-// 18 segments, and the wavefronts of neighbouring strips share it: DRAM
-// pages are reused instead of 36 planes megabytes apart being streamed.
+// Layout: row-major rows; within a row the 18 populations q = 9 k + i of a
+// node are packed into vector planes of `pitch` nodes: four float4 planes
+// (q = 0-3, 4-7, 8-11, 12-15, i.e. f_A0..3, f_A4..7, f_A8 f_B0..2, f_B3..6)
+// and one float2 plane (q = 16, 17: f_B7, f_B8), 18 pitch floats per row.
+// The two density deviations of a node are one float2, rho[y][x][k].  A
+// wavefront working on one lattice row then moves each plane of 64
+// consecutive nodes with one 16-byte (8-byte) access per lane, 1 KiB per
+// instruction; single-float accesses per lane would reach only about two
+// thirds of the bandwidth of wide ones on this GPU.
 //
 // Numerical formulation (FP32 throughout the step):
 //   * the density deviation sum is accumulated in FP64 and rounded once, so
@@ -114,13 +118,13 @@ __device__ __forceinline__ float psi_of(const Par &P, float r)
 // index of population q = 9 k + i of node (x, y) in a population buffer
 __device__ __forceinline__ int64_t fidx(const KInst &P, int q, int x, int y)
 {
-    return ((int64_t)y * 18 + q) * P.pitch + x;
+    return ((int64_t)y * 18 + (q & ~3)) * P.pitch + (int64_t)x * (q < 16 ? 4 : 2) + (q & 3);
 }
 
 // index of the density deviation of component k of node (x, y)
 __device__ __forceinline__ int64_t ridx(const KInst &P, int k, int x, int y)
 {
-    return ((int64_t)y * 2 + k) * P.pitch + x;
+    return ((int64_t)y * P.pitch + x) * 2 + k;
 }
 
 // Populations of node (x, y) from buffer fb (D2Q9 order 0:(0,0) 1:(1,0)

@@ -69,6 +69,39 @@ __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// 16- and 8-byte loads, 8-byte stores through a buffer descriptor (raw bits)
+__device__ __forceinline__ u32x4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+
+__device__ __forceinline__ u32x2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+}
+
+__device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                        uint32_t soff)
+{
+    u32x2 v = {__float_as_uint(a), __float_as_uint(b)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+}
+
+// A float4 plane entry as two 8-byte stores.  A 16-byte buffer store with a
+// register soffset whose data registers the very next VALU instruction
+// overwrote (a 64-bit result) stored the new values on this GPU under load;
+// the compiler inserts no wait for that form.  8-byte stores, which bandwidth
+// does not distinguish from 16-byte ones here, showed no such window.
+__device__ __forceinline__ void bstore4(float a, float b, float c, float d,
+                                        __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    bstore2(a, b, r, voff, soff);
+    bstore2(c, d, r, voff, soff + 8u);
+}
+
 // Lane shifts of a wavefront through DPP (lane l receives lane l - 1, resp.
 // l + 1; the end lanes keep their own value and are never consumed).
 __device__ __forceinline__ float from_left(float v)
@@ -133,8 +166,14 @@ struct RingAccW {
 // 1 the velocity shift of the original model (momenta without F/2, BGK
 // towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
+// Register budget: three waves per SIMD (168 VGPRs) for strips of two and
+// four wavefronts, which the fastest plans keep near two waves per SIMD
+// anyway; at four (128 VGPRs) the step spills, and the spill reload's wait
+// drains the row's outstanding stores.  One-wave strips fit in 128; eight-wave
+// strips keep two workgroups per CU at 128 with a small spill.
 template <int NW, int FS>
-__global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restrict__ insts,
+__global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused_step(
+    const KInst *__restrict__ insts,
                                                          const int4 *__restrict__ segs,
                                                          const int *__restrict__ first, int par)
 {
@@ -155,22 +194,22 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
     const int L = (int)threadIdx.x;
     const int l = L & 63, wv = L >> 6;
     const int nx = G.nx, ny = G.ny, walls = G.walls;
-    const uint32_t qb = (uint32_t)G.pitch * 4u;   // bytes per row segment
-    const uint32_t frowb = 18u * qb;              // bytes per population row
-    const uint32_t rrowb = 2u * qb;               // bytes per density row
+    const uint32_t pb = (uint32_t)G.pitch;        // nodes per row (with padding)
+    const uint32_t frowb = 72u * pb;              // bytes per population row
+    const uint32_t rrowb = 8u * pb;               // bytes per density row
     const __amdgpu_buffer_rsrc_t fin = make_rsrc(G.f[par], (uint32_t)ny * frowb);
     const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
     const __amdgpu_buffer_rsrc_t rin = make_rsrc(G.rho[par], (uint32_t)ny * rrowb);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(G.rho[par ^ 1], (uint32_t)ny * rrowb);
-    const uint32_t xcb = (uint32_t)wrapi(X0 - 1 + L, nx) * 4u;  // collided column, bytes
+    const uint32_t xc = (uint32_t)wrapi(X0 - 1 + L, nx);  // collided column
     const bool outl = (L >= 1) && (L <= wo);
     constexpr uint32_t DROP = 0x80000000u;  // out-of-range offset: store dropped
     // ring column j holds lattice column X0 - 1 - HALO + j; thread L fills
     // j = L (both components) and one (extra column, component) pair: lanes
     // with the same pair load the same value and write it to the same place
-    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 4u;
+    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 8u;
     const int xe = l & 3, ke = (l >> 2) & 1;
-    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 4u + (ke ? qb : 0u);
+    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 8u + (uint32_t)ke * 4u;
     // per-lane parameters of the extra column's component, selected once (a
     // lane-dependent index into the parameter copy would put it in scratch)
     const float ref_e = ke ? P.rho_ref[1] : P.rho_ref[0];
@@ -199,9 +238,10 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
     // rows beyond a wall read row 0 (valid memory); ring_store replaces the values
     auto ring_load = [&](int ri) {
         const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * rrowb;
+        const u32x2 ab = bload2(rin, ro + gx0b, 0);
         RingVals v;
-        v.a = bload(rin, ro + gx0b, 0);
-        v.b = bload(rin, ro + gx0b, qb);
+        v.a = __uint_as_float(ab.x);
+        v.b = __uint_as_float(ab.y);
         v.e = bload(rin, ro + gxeb, 0);
         return v;
     };
@@ -220,12 +260,25 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
         R.rho[ke][slot][NL + xe] = re;
         R.psi[ke][slot][NL + xe] = wall ? pwall_e : psi_of(P, re);
     };
+    // four float4 planes and one float2 plane per row (q = 9 k + i in order)
     auto load_f = [&](int ri, float f[2][9]) {
-        const uint32_t off = (uint32_t)(ri < 0 ? 0 : ri) * frowb + xcb;
+        const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * frowb;
+        float q[18];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const u32x4 v = bload4(fin, ro + xc * 16u, (uint32_t)g * 16u * pb);
+            q[4 * g + 0] = __uint_as_float(v.x);
+            q[4 * g + 1] = __uint_as_float(v.y);
+            q[4 * g + 2] = __uint_as_float(v.z);
+            q[4 * g + 3] = __uint_as_float(v.w);
+        }
+        const u32x2 w = bload2(fin, ro + xc * 8u, 64u * pb);
+        q[16] = __uint_as_float(w.x);
+        q[17] = __uint_as_float(w.y);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[k][i] = bload(fin, off, (uint32_t)(k * 9 + i) * qb);
+            for (int i = 0; i < 9; ++i) f[k][i] = q[9 * k + i];
     };
 
     // ring rows Y0 - 3 .. Y0 + 1 into slots 0..4; slot[d] is the slot of row
@@ -331,10 +384,14 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
             const int o = cc.r - 1;
             const bool wlo = walls && o == 0;
             const bool whi = walls && o == ny - 1;
-            const uint32_t off =
-                (outl && it >= 2) ? (uint32_t)o * frowb + (uint32_t)(X0 - 1 + L) * 4u : DROP;
-            const uint32_t roff =
-                (outl && it >= 2) ? (uint32_t)o * rrowb + (uint32_t)(X0 - 1 + L) * 4u : DROP;
+            const bool st = outl && it >= 2;
+            const uint32_t xo = (uint32_t)(X0 - 1 + L);
+            const uint32_t off4 = st ? (uint32_t)o * frowb + xo * 16u : DROP;
+            const uint32_t off2 = st ? (uint32_t)o * frowb + xo * 8u : DROP;
+            const uint32_t roff = st ? (uint32_t)o * rrowb + xo * 8u : DROP;
+            // component A fills planes 0, 1 and the first lane of plane 2;
+            // component B the rest of plane 2, plane 3 and the float2 plane
+            float a8 = 0.0f, ra = 0.0f;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 float g[9];
@@ -357,9 +414,17 @@ __global__ __launch_bounds__(64 * NW, 4) void k_fused_step(const KInst *__restri
                 g[4] = whi ? Sprev[k][2] : S[k][4];
                 g[7] = whi ? Sprev[k][5] : r7;
                 g[8] = whi ? Sprev[k][6] : l8;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) bstore(g[i], fout, off, (uint32_t)(k * 9 + i) * qb);
-                bstore(sum9(g), rout, roff, (uint32_t)k * qb);
+                if (k == 0) {
+                    bstore4(g[0], g[1], g[2], g[3], fout, off4, 0u);
+                    bstore4(g[4], g[5], g[6], g[7], fout, off4, 16u * pb);
+                    a8 = g[8];
+                    ra = sum9(g);
+                } else {
+                    bstore4(a8, g[0], g[1], g[2], fout, off4, 32u * pb);
+                    bstore4(g[3], g[4], g[5], g[6], fout, off4, 48u * pb);
+                    bstore2(g[7], g[8], fout, off2, 64u * pb);
+                    bstore2(ra, sum9(g), rout, roff, 0u);
+                }
             }
         }
 #pragma unroll
