@@ -154,9 +154,10 @@ struct RingAccW {
 //     node's own reflected population next to a wall;
 //   * f(t+1) and rho(t+1) of the output row are written.
 // The loop body has no lane-divergent branches on global memory: every lane
-// loads a valid column (idle lanes a neighbour's), rows beyond a wall read a
-// clamped row whose values are not used, and lanes that must not write give
-// an offset beyond the buffer, which the descriptor's range check drops
+// loads a valid column or, where nothing it loads is used (idle lanes beyond
+// the halo), zeros, rows beyond a wall read a clamped row whose values are
+// not used, and lanes that must not write give an offset beyond the buffer,
+// which the descriptor's range check drops
 // (buffers stay below 2 GiB, so that offset plus any segment offset cannot
 // wrap into range).  Memory waits are then exact.  The next row's
 // populations are loaded while the current row is collided.  Two barriers
@@ -166,13 +167,13 @@ struct RingAccW {
 // 1 the velocity shift of the original model (momenta without F/2, BGK
 // towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
 // Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
-// Register budget: three waves per SIMD (168 VGPRs) for strips of two and
-// four wavefronts, which the fastest plans keep near two waves per SIMD
-// anyway; at four (128 VGPRs) the step spills, and the spill reload's wait
-// drains the row's outstanding stores.  One-wave strips fit in 128; eight-wave
-// strips keep two workgroups per CU at 128 with a small spill.
+// Register budget: three waves per SIMD (168 VGPRs) for strips of two or
+// more wavefronts, which the fastest plans keep at two waves per SIMD or
+// fewer anyway (eight-wave strips: one workgroup per CU); at four (128
+// VGPRs) the step spills, and the spill reload's wait drains the row's
+// outstanding stores.  One-wave strips fit in 128.
 template <int NW, int FS>
-__global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused_step(
+__global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
     const KInst *__restrict__ insts,
                                                          const int4 *__restrict__ segs,
                                                          const int *__restrict__ first, int par)
@@ -203,13 +204,24 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(G.rho[par ^ 1], (uint32_t)ny * rrowb);
     const uint32_t xc = (uint32_t)wrapi(X0 - 1 + L, nx);  // collided column
     const bool outl = (L >= 1) && (L <= wo);
-    constexpr uint32_t DROP = 0x80000000u;  // out-of-range offset: store dropped
+    // out-of-range offset: a load returns 0 without a memory request, a store
+    // is dropped (offsets below 2 GiB plus this one cannot wrap into range)
+    constexpr uint32_t DROP = 0x80000000u;
+    // lanes beyond the right halo column (L > wo + 1) collide values that no
+    // output uses: their population loads read zeros instead of memory
+    const bool needf = L <= wo + 1;
+    const uint32_t xf16 = needf ? xc * 16u : DROP, xf8 = needf ? xc * 8u : DROP;
     // ring column j holds lattice column X0 - 1 - HALO + j; thread L fills
     // j = L (both components) and one (extra column, component) pair: lanes
-    // with the same pair load the same value and write it to the same place
-    const uint32_t gx0b = (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 8u;
+    // with the same pair load the same value and write it to the same place.
+    // The stencils of lanes 0 .. wo + 1 read columns up to wo + 1 + 2 HALO;
+    // columns beyond are filled from zeros.
+    const int jmax = wo + 1 + 2 * HALO;
+    const uint32_t gx0b = L <= jmax ? (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 8u : DROP;
     const int xe = l & 3, ke = (l >> 2) & 1;
-    const uint32_t gxeb = (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 8u + (uint32_t)ke * 4u;
+    const uint32_t gxeb = NL + xe <= jmax
+                              ? (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 8u + (uint32_t)ke * 4u
+                              : DROP;
     // per-lane parameters of the extra column's component, selected once (a
     // lane-dependent index into the parameter copy would put it in scratch)
     const float ref_e = ke ? P.rho_ref[1] : P.rho_ref[0];
@@ -235,14 +247,16 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
     struct RingVals {
         float a, b, e;  // density deviations of A, B at column L; extra-column value
     };
-    // rows beyond a wall read row 0 (valid memory); ring_store replaces the values
-    auto ring_load = [&](int ri) {
+    // rows beyond a wall read row 0 (valid memory); ring_store replaces the
+    // values.  A row that no later collision needs (live false: the loads of
+    // the last iteration) reads zeros instead of memory.
+    auto ring_load = [&](int ri, bool live) {
         const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * rrowb;
-        const u32x2 ab = bload2(rin, ro + gx0b, 0);
+        const u32x2 ab = bload2(rin, live ? ro + gx0b : DROP, 0);
         RingVals v;
         v.a = __uint_as_float(ab.x);
         v.b = __uint_as_float(ab.y);
-        v.e = bload(rin, ro + gxeb, 0);
+        v.e = bload(rin, live ? ro + gxeb : DROP, 0);
         return v;
     };
     auto ring_store = [&](int slot, int ri, const RingVals &v) {
@@ -255,24 +269,27 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
         R.psi[1][slot][L] = wall ? P.psi_wall[1] : psi_of(P, rb);
         R.dev[0][slot][L] = v.a;
         R.dev[1][slot][L] = v.b;
-        const float re = wall ? rwall_e : ref_e + v.e;
-        R.dev[ke][slot][NL + xe] = v.e;
-        R.rho[ke][slot][NL + xe] = re;
-        R.psi[ke][slot][NL + xe] = wall ? pwall_e : psi_of(P, re);
+        if (NL <= jmax) {  // uniform: the strip's stencils reach the extra columns
+            const float re = wall ? rwall_e : ref_e + v.e;
+            R.dev[ke][slot][NL + xe] = v.e;
+            R.rho[ke][slot][NL + xe] = re;
+            R.psi[ke][slot][NL + xe] = wall ? pwall_e : psi_of(P, re);
+        }
     };
     // four float4 planes and one float2 plane per row (q = 9 k + i in order)
-    auto load_f = [&](int ri, float f[2][9]) {
+    auto load_f = [&](int ri, bool live, float f[2][9]) {
         const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * frowb;
+        const uint32_t o16 = live ? ro + xf16 : DROP, o8 = live ? ro + xf8 : DROP;
         float q[18];
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const u32x4 v = bload4(fin, ro + xc * 16u, (uint32_t)g * 16u * pb);
+            const u32x4 v = bload4(fin, o16, (uint32_t)g * 16u * pb);
             q[4 * g + 0] = __uint_as_float(v.x);
             q[4 * g + 1] = __uint_as_float(v.y);
             q[4 * g + 2] = __uint_as_float(v.z);
             q[4 * g + 3] = __uint_as_float(v.w);
         }
-        const u32x2 w = bload2(fin, ro + xc * 8u, 64u * pb);
+        const u32x2 w = bload2(fin, o8, 64u * pb);
         q[16] = __uint_as_float(w.x);
         q[17] = __uint_as_float(w.y);
 #pragma unroll
@@ -286,7 +303,7 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
     int slot[RR];
     Cursor cr = cursor(Y0 - 1 - HALO);  // next row to enter the ring
     for (int q = 0; q < RR; ++q) {
-        ring_store(q, cr.i, ring_load(cr.i));
+        ring_store(q, cr.i, ring_load(cr.i, true));
         slot[q] = q;
         advance(cr);
     }
@@ -295,7 +312,7 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
     Cursor cc = cursor(Y0 - 1);  // row being collided
     Cursor cf = cc;              // row of the prefetched populations
     float fn[2][9];
-    load_f(cf.i, fn);
+    load_f(cf.i, true, fn);
     float Sprev[2][9], Uprev[2][3];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -307,16 +324,17 @@ __global__ __launch_bounds__(64 * NW, (NW == 2 || NW == 4) ? 3 : 4) void k_fused
     const int nit = ho + 2;
     for (int it = 0; it < nit; ++it) {
         // the next density row first, then the next population row (the last
-        // iteration reads rows beyond the strip: valid and unused)
+        // iteration needs neither: its loads read zeros)
+        const bool more = it + 1 < nit;
         const int rnext = cr.i;
-        const RingVals vnext = ring_load(rnext);
+        const RingVals vnext = ring_load(rnext, more);
         float f[2][9];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[k][i] = fn[k][i];
         advance(cf);
-        load_f(cf.i, fn);
+        load_f(cf.i, more, fn);
 
         // collide row c (a row beyond a wall is collided from clamped data
         // and never used)

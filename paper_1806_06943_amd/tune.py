@@ -9,7 +9,11 @@ simulation.  Widths cover strips of 1, 2, 4 and 8 wavefronts, each either
 balanced (64 n - 2 columns) or placed at multiples of a multiple of 16
 columns (output rows start on 64-byte boundaries); for each width the
 uniform plans (chunks of a candidate height) and the balanced plans (1 to 4
-workgroups per compute unit, equal shares of rows) are timed.
+workgroups per compute unit, equal shares of rows) are timed.  Beside a fixed
+list of heights, each width gets the heights fitted to the GPU: for k = 1..4
+the smallest height whose launch has at most k workgroups per compute unit
+(a launch just past such a multiple leaves most compute units idle for its
+last round of workgroups).
 """
 from __future__ import annotations
 
@@ -19,6 +23,7 @@ import os
 from . import lbm
 
 CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
+MIN_HEIGHT = 4  # the smallest strip height lbm_set_tiling accepts
 # (output columns per strip): one wavefront per strip, balanced / aligned,
 # then strips of 2, 4 and 8 wavefronts, balanced / aligned
 WIDTHS = (62, 48, 126, 112, 254, 240, 510, 496)
@@ -28,7 +33,7 @@ CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), "
 
 def _key(sim, arch: str) -> str:
     shapes = sorted({(p.nx, p.ny) for p in sim.params})
-    return f"{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
+    return f"v2|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
         (f"|+{len(shapes) - 8}" if len(shapes) > 8 else "")
 
 
@@ -52,6 +57,36 @@ def apply(sim, width: int, height: int, balance: int = 0):
         lbm.lbm_set_tiling(sim.ctx, int(height))
 
 
+def _ncu(sim) -> int:
+    try:
+        return int(sim.torch.cuda.get_device_properties(sim.device).multi_processor_count)
+    except Exception:
+        return 256
+
+
+def fitted_heights(sim, width: int, ncu: int, kmax: int = 4) -> list:
+    """For k = 1..kmax the smallest uniform strip height at which the launch has at
+    most k * ncu workgroups (the count falls as the height grows)."""
+    hmin = MIN_HEIGHT
+    hmax = max(max(p.ny for p in sim.params), hmin)
+    out = set()
+    for k in range(1, kmax + 1):
+        target = k * ncu
+        apply(sim, width, hmax)
+        if lbm.lbm_get_workgroups(sim.ctx) > target:
+            continue
+        lo, hi = hmin, hmax
+        while lo < hi:
+            mid = (lo + hi) // 2
+            apply(sim, width, mid)
+            if lbm.lbm_get_workgroups(sim.ctx) <= target:
+                hi = mid
+            else:
+                lo = mid + 1
+        out.add(lo)
+    return sorted(out)
+
+
 def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
          widths=WIDTHS, balances=BALANCES) -> dict:
     """Pick the fastest strip shape for sim's context; returns the timings."""
@@ -69,8 +104,9 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
         apply(sim, e["width"], e["best"], e["balance"])
         return e
     times = {}
+    ncu = _ncu(sim)
     for wdt in widths:
-        for h in candidates:
+        for h in sorted(set(candidates) | set(fitted_heights(sim, wdt, ncu))):
             apply(sim, wdt, h)
             lbm.lbm_profile_step(sim.ctx, 3)  # warm-up
             times[(wdt, h, 0)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]

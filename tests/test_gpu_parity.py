@@ -331,6 +331,26 @@ def test_small_and_ragged_lattices(torch, nx, ny, walls):
     assert np.abs(got - fo).max() < 1e-6
 
 
+@pytest.mark.parametrize("width", [510, 240, 126])
+def test_fitted_heights_sit_just_under_cu_multiples(torch, width):
+    """The tuner's fitted heights: at h the launch has at most k CUs' worth of
+    workgroups, at h - 1 more (2048 x 2048 lattice; host planning only)."""
+    w = W.spinodal(nx=2048, ny=2048)
+    sim = lbm.Sim([lbm.workload_instance(w)])
+    ncu = tune._ncu(sim)
+    hs = tune.fitted_heights(sim, width, ncu)
+    assert hs
+    for h in hs:
+        tune.apply(sim, width, h)
+        n = lbm.lbm_get_workgroups(sim.ctx)
+        k = -(-n // ncu)
+        assert n <= k * ncu
+        if h > 1:
+            tune.apply(sim, width, h - 1)
+            assert lbm.lbm_get_workgroups(sim.ctx) > k * ncu, (h, n)
+    sim.close()
+
+
 def test_strip_height_does_not_change_results(torch):
     """The strip height only moves work between wavefronts: results are bitwise equal."""
     w = W.emulsion(nx=200, ny=96, ndrop=4, radius=9, gx=1e-5)
