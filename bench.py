@@ -142,7 +142,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
     ms_fwd = timed(torch, fwd.stream, lambda: fwd.step(steps))
     fwd.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
-    tune.apply(prob.sim, tuning["width"], tuning["best"], tuning.get("balance", 0))
+    for s in (prob.sim, prob.rec):  # forward context and window re-run context
+        tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0))
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -8,7 +8,10 @@ differentiated in reverse mode with checkpoint-and-recompute: the forward
 pass keeps the state at the start of each window of steps; the backward pass
 re-runs each window forward from its checkpoint, storing its states, and
 applies the library's adjoint step (``lbm_adjoint_step``) backwards through
-the window.  Memory: one state per window boundary plus ``window`` states.
+the window.  The re-run of the window before runs meanwhile, in a second
+library context on a second stream, into the other of two state stores
+(events order each store's reuse), so the two latency-bound passes overlap.
+Memory: one state per window boundary plus two windows of states.
 
 Argument marshalling and bookkeeping only: the step, the adjoint step and the
 objective seeds all run in the HIP library.
@@ -33,6 +36,10 @@ class Problem:
             raise ValueError("steps must be >= 0 and window >= 1")
         self.sim = lbm.Sim([instance], device=device)
         self.torch = self.sim.torch
+        # the context that re-runs windows, on a stream of its own (default
+        # priority), beside the adjoint sweep of the following window
+        self.rec = lbm.Sim([instance], device=device,
+                           stream=self.torch.cuda.Stream(device=self.sim.device))
         self.steps = int(steps)
         self.window = int(window)
         self.objective = objective
@@ -75,23 +82,41 @@ class Problem:
         t = self.torch
         theta, ckpts, lamT, direct = saved
         self.sim.set_theta(theta)
-        if self._store is None or self._store.shape[0] < min(self.window, max(self.steps, 1)):
-            self._store = t.empty((min(self.window, max(self.steps, 1)),) + self.shape,
-                                  dtype=t.float32, device=self.sim.device)
+        m = min(self.window, max(self.steps, 1))
+        if self._store is None or self._store.shape[1] < m:
+            self._store = t.empty((2, m) + self.shape, dtype=t.float32, device=self.sim.device)
         S = self._store
         grad = t.zeros(5, dtype=t.float64, device=self.sim.device)
         lam = lamT.clone()
         tmp = t.empty_like(lam)
         wins = self._windows()
-        ctx = self.sim.ctx
+        rec, adj = self.rec, self.sim
+        rec.set_theta(theta)
+        # the checkpoints and the seed come from the adjoint context's stream
+        rec.stream.wait_stream(adj.stream)
+        recorded = [t.cuda.Event(), t.cuda.Event()]
+        released = [None, None]  # event after the last adjoint sweep that read a store
+
+        def rerun(w):
+            # the window from its checkpoint, keeping the state before each step
+            b = w % 2
+            if released[b] is not None:
+                rec.stream.wait_event(released[b])
+            rec.set_populations(ckpts[w])
+            lbm.lbm_record(rec.ctx, 0, wins[w][1], S[b].data_ptr())
+            recorded[b].record(rec.stream)
+
+        if wins:
+            rerun(len(wins) - 1)
         for w in range(len(wins) - 1, -1, -1):
-            _, n = wins[w]
-            # re-run the window from its checkpoint, keeping the state before each
-            # step, then the adjoint steps back through it (two library calls)
-            self.sim.set_populations(ckpts[w])
-            lbm.lbm_record(ctx, 0, n, S.data_ptr())
-            lbm.lbm_adjoint_run(ctx, 0, n, S.data_ptr(), lam.data_ptr(), tmp.data_ptr(),
-                                grad.data_ptr())
+            b = w % 2
+            adj.stream.wait_event(recorded[b])
+            lbm.lbm_adjoint_run(adj.ctx, 0, wins[w][1], S[b].data_ptr(), lam.data_ptr(),
+                                tmp.data_ptr(), grad.data_ptr())
+            released[b] = t.cuda.Event()
+            released[b].record(adj.stream)
+            if w > 0:
+                rerun(w - 1)
         g = grad.cpu().numpy() + direct
         return g, lam
 
@@ -102,6 +127,7 @@ class Problem:
         return J, g, lam0
 
     def close(self):
+        self.rec.close()
         self.sim.close()
 
 

@@ -194,26 +194,30 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
     if (x < A.nx && y < A.ny) {
         const int cx = lx + HALO, cy = ly + HALO;
         float rho[2], psi[2], drho[2], mx[2], my[2], F[2][2];
-        double s1[2][2], s2[2][2], sr[2][2];
-        float dev[2][9];
+        // the three stencil sums of a component at this node (FP64)
+        auto sums = [&](int k, double (&s1)[2], double (&s2)[2], double (&sr)[2]) {
+            auto vp = [&](int dx, int dy) { return T.psi[k][cy + dy][cx + dx]; };
+            auto vr = [&](int dx, int dy) { return T.rho[1 - k][cy + dy][cx + dx]; };
+            sum9s<double>(vp, DW1, DW2, s1[0], s1[1]);
+            sum25<double>(vp, DP1, DP2, DP4, DP5, DP8, s2[0], s2[1]);
+            sum9s<double>(vr, DW1, DW2, sr[0], sr[1]);
+        };
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
+            float dev[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dev[k][i] = f[xidx(A, k * 9 + i, x, y)];
+            for (int i = 0; i < 9; ++i) dev[i] = f[xidx(A, k * 9 + i, x, y)];
             rho[k] = T.rho[k][cy][cx];
             psi[k] = T.psi[k][cy][cx];
             drho[k] = A.scr[sidx(A, SCR_RDEV + k, x, y)];
-            mx[k] = (dev[k][1] - dev[k][3]) + (dev[k][5] - dev[k][7]) + (dev[k][8] - dev[k][6]);
-            my[k] = (dev[k][2] - dev[k][4]) + (dev[k][5] - dev[k][7]) + (dev[k][6] - dev[k][8]);
-            auto vp = [&](int dx, int dy) { return T.psi[k][cy + dy][cx + dx]; };
-            auto vr = [&](int dx, int dy) { return T.rho[1 - k][cy + dy][cx + dx]; };
-            sum9s<double>(vp, DW1, DW2, s1[k][0], s1[k][1]);
-            sum25<double>(vp, DP1, DP2, DP4, DP5, DP8, s2[k][0], s2[k][1]);
-            sum9s<double>(vr, DW1, DW2, sr[k][0], sr[k][1]);
+            mx[k] = (dev[1] - dev[3]) + (dev[5] - dev[7]) + (dev[8] - dev[6]);
+            my[k] = (dev[2] - dev[4]) + (dev[5] - dev[7]) + (dev[6] - dev[8]);
+            double s1[2], s2[2], sr[2];
+            sums(k, s1, s2, sr);
 #pragma unroll
             for (int d = 0; d < 2; ++d)
-                F[k][d] = (float)(-(double)psi[k] * ((double)A.G1[k] * s1[k][d] + (double)A.G2[k] * s2[k][d]) -
-                                  (double)A.gab * (double)rho[k] * sr[k][d]) +
+                F[k][d] = (float)(-(double)psi[k] * ((double)A.G1[k] * s1[d] + (double)A.G2[k] * s2[d]) -
+                                  (double)A.gab * (double)rho[k] * sr[d]) +
                           rho[k] * A.g[k][d];
         }
         float jx[2], jy[2];
@@ -226,6 +230,11 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
         const float iD = 1.0f / D;
         const float ux = (jx[0] * A.it[0] + jx[1] * A.it[1]) * iD;
         const float uy = (jy[0] * A.it[0] + jy[1] * A.it[1]) * iD;
+        // Compiler-only barrier (no instruction): the populations and the
+        // stencil sums are read again below instead of being held in
+        // registers across the FP64 transpose, which keeps the kernel within
+        // the register budget of two wavefronts per SIMD.
+        asm volatile("" ::: "memory");
 
         // The transpose is evaluated in FP64 from the FP32 linearisation point:
         // for adjoints of conserved or nearly conserved quantities its terms
@@ -276,7 +285,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                     ubx += ai * c * w * (-3.0 * Fx + 9.0 * eF * ex);
                     uby += ai * c * w * (-3.0 * Fy + 9.0 * eF * ey);
                     // f - feq in deviation form: dev - w (drho + rho (E - 1))
-                    const R fneq = (R)dev[k][i] - w * ((R)drho[k] + rk * Em1);
+                    const R fneq = (R)f[xidx(A, k * 9 + i, x, y)] - w * ((R)drho[k] + rk * Em1);
                     gt += ai * fneq;
                     gg += ai * w * (gx * Fx + gy * Fy);
                 }
@@ -319,9 +328,11 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
         // own-node terms of the force transpose and the coupling gradients
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const R s1F = s1[k][0] * Fb[k][0] + s1[k][1] * Fb[k][1];
-            const R s2F = s2[k][0] * Fb[k][0] + s2[k][1] * Fb[k][1];
-            const R srF = sr[k][0] * Fb[k][0] + sr[k][1] * Fb[k][1];
+            double s1[2], s2[2], sr[2];
+            sums(k, s1, s2, sr);
+            const R s1F = s1[0] * Fb[k][0] + s1[1] * Fb[k][1];
+            const R s2F = s2[0] * Fb[k][0] + s2[1] * Fb[k][1];
+            const R srF = sr[0] * Fb[k][0] + sr[1] * Fb[k][1];
             const R psibar = -((R)A.G1[k] * s1F + (R)A.G2[k] * s2F);
             const R rown = psibar * (R)expf(-rho[k] * A.inv_rho0) - (R)A.gab * srF +
                            (R)A.g[k][0] * Fb[k][0] + (R)A.g[k][1] * Fb[k][1];

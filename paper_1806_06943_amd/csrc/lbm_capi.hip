@@ -763,10 +763,11 @@ static AdjPar adj_par(const lbm_ctx *ctx, int inst)
     return A;
 }
 
-static bool overlaps(const void *a, const void *b, uint64_t n)
+// [a, a + na) and [b, b + nb) share a byte
+static bool overlaps(const void *a, uint64_t na, const void *b, uint64_t nb)
 {
     const char *x = (const char *)a, *y = (const char *)b;
-    return x < y + n && y < x + n;
+    return x < y + nb && y < x + na;
 }
 
 int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
@@ -780,7 +781,7 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float
     if (!f_dev || !lam_in_dev || !lam_out_dev) return fail(ctx, LBM_EINVAL, "null argument");
     const lbm_params &p = ctx->params[inst];
     const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
-    if (overlaps(lam_out_dev, lam_in_dev, nb) || overlaps(lam_out_dev, f_dev, nb))
+    if (overlaps(lam_out_dev, nb, lam_in_dev, nb) || overlaps(lam_out_dev, nb, f_dev, nb))
         return fail(ctx, LBM_EINVAL, "lam_out must not overlap f or lam_in");
     hipError_t e = launch_adjoint_step(adj_par(ctx, inst), f_dev, lam_in_dev, lam_out_dev, grad_dev,
                                        ctx->stream);
@@ -842,9 +843,9 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     const lbm_params &p = ctx->params[inst];
     const int64_t N = (int64_t)18 * p.nx * p.ny;
     const uint64_t nb = (uint64_t)N * sizeof(float);
-    if (overlaps(lam_dev, tmp_dev, nb)) return fail(ctx, LBM_EINVAL, "lam and tmp overlap");
-    if (nsteps > 0 && (overlaps(lam_dev, f_store_dev, nb * nsteps) ||
-                       overlaps(tmp_dev, f_store_dev, nb * nsteps)))
+    if (overlaps(lam_dev, nb, tmp_dev, nb)) return fail(ctx, LBM_EINVAL, "lam and tmp overlap");
+    if (nsteps > 0 && (overlaps(lam_dev, nb, f_store_dev, nb * nsteps) ||
+                       overlaps(tmp_dev, nb, f_store_dev, nb * nsteps)))
         return fail(ctx, LBM_EINVAL, "lam or tmp overlaps the state store");
     if (nsteps == 0) return LBM_OK;
     const AdjPar A = adj_par(ctx, inst);
@@ -877,7 +878,7 @@ int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, int32_t objective, const float 
         return fail(ctx, LBM_EINVAL, "the flow-rate objective needs lam_dev");
     const lbm_params &p = ctx->params[inst];
     const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
-    if (lam_dev && overlaps(lam_dev, f_dev, nb))
+    if (lam_dev && overlaps(lam_dev, nb, f_dev, nb))
         return fail(ctx, LBM_EINVAL, "lam_dev must not overlap f_dev");
     const AdjPar A = adj_par(ctx, inst);
     hipStream_t st = ctx->stream;

@@ -188,6 +188,27 @@ def test_conserved_objectives_have_zero_gradient(torch):
         assert np.abs(g).max() <= 1e-4 * scale, (which, g, scale)
 
 
+@pytest.mark.parametrize("which", ["dp", "momA"])
+def test_gradient_does_not_depend_on_the_window(torch, which):
+    """Windows re-run on a second stream while the adjoint sweeps the next one:
+    J and dJ/df(0) must equal those of one window bit for bit (the re-run
+    states are deterministic); the parameter gradient to FP64 rounding (each
+    window's per-block partial sums are folded into it at the window's end, so
+    the order of the FP64 additions depends on the window)."""
+    say("windows", which)
+    d = droplet_instance(64, 48, 0, R=12, g=1e-5)
+    out = []
+    for window in (120, 25, 7):
+        prob = AD.Problem(d, steps=120, objective=which, window=window)
+        J, g, lam0 = prob.value_and_grad()
+        out.append((J, g, lam0.cpu().numpy()))
+        prob.close()
+    for J, g, lam0 in out[1:]:
+        assert J == out[0][0]
+        assert np.array_equal(lam0, out[0][2])
+        assert np.abs(g - out[0][1]).max() <= 1e-12 * np.abs(out[0][1]).max(), (g, out[0][1])
+
+
 def test_autograd_function_and_finite_differences(torch):
     say("autograd")
     d = droplet_instance(48, 48, 0, R=12, g=1e-5)
