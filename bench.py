@@ -89,10 +89,12 @@ def parse():
 
 # algorithmic bytes per lattice update of the adjoint kernels (FP32):
 #   k_adj_density: read 18 populations, write 2 densities            = 80
-#   k_adj_local:   read 18 populations, 18 adjoints, 2 densities,
-#                  write 18 adjoints, 4 force adjoints               = 240
-#   k_adj_force:   read 4 force adjoints, 2 densities, read+write 18 = 168
-ADJ_B_PER_LU = {"k_adj_density": 80.0, "k_adj_local": 240.0, "k_adj_force": 168.0}
+#   k_adj_local:   read 18 populations, 18 adjoints, 2 densities and
+#                  the 2 pending additions, write 18 adjoints and
+#                  4 force adjoints                                  = 248
+#   k_adj_force:   read 4 force adjoints and 2 densities, write the
+#                  2 additions to every adjoint of a component       = 32
+ADJ_B_PER_LU = {"k_adj_density": 80.0, "k_adj_local": 248.0, "k_adj_force": 32.0}
 
 
 def timed(torch, stream, fn):

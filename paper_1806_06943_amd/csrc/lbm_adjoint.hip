@@ -259,7 +259,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                 const int ys = bounce ? y : wrapi(yd, A.ny);
                 const int is = bounce ? c_op[i] : i;
 #pragma unroll
-                for (int k = 0; k < 2; ++k) a[k][i] = lam_next[xidx(A, k * 9 + is, xs, ys)];
+                for (int k = 0; k < 2; ++k)
+                    a[k][i] = lam_next[xidx(A, k * 9 + is, xs, ys)] +
+                              A.scr[sidx(A, SCR_ADD + k, xs, ys)];
             }
             // transpose of Eq. 1 (BGK + Guo) at fixed rho_k, u, F_k
             R ubx = 0.0, uby = 0.0, rbar[2];
@@ -365,13 +367,15 @@ __global__ __launch_bounds__(256) void k_adj_zero(AdjPar A, int n)
 //   psibar_k(y) = sum_e c_k(e) e . (q_k(y + e) - q_k(y - e))   (e over half of D2Q25,
 //                 c_k(e) = G1_k w(e) + G2_k p(e))
 //   rhobar_kb(y) += G_AB sum_e w(e) e . (r_k(y + e) - r_k(y - e))   (half of D2Q9)
-// and lam_{k,i}(y) += psibar_k(y) exp(-rho_k / rho0) + rhobar_k(y).
+// and lam_{k,i}(y) += psibar_k(y) exp(-rho_k / rho0) + rhobar_k(y), the same for
+// all i: the kernel writes that addition per component (SCR_ADD), and the
+// next step's gather, or the combine pass, adds it where lam is read.
 struct QTile {
     float q[2][2][AH][AW];  // [k][d]
     float r[2][2][AH][AW];
 };
 
-__global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A, float *__restrict__ lam)
+__global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A)
 {
     __shared__ QTile T;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -422,9 +426,32 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A, float *__restr
         (void)dx_;
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 2; ++k) A.scr[sidx(A, SCR_ADD + k, x, y)] = add[k];
+}
+
+// out_{k,i} = in_{k,i} + add_k (the pending force-transpose addition)
+__global__ __launch_bounds__(NTHREADS) void k_adj_combine(AdjPar A, const float *in,
+                                                          float *out)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    if (x >= A.nx || y >= A.ny) return;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lam[xidx(A, k * 9 + i, x, y)] += add[k];
+    for (int k = 0; k < 2; ++k) {
+        const float a = A.scr[sidx(A, SCR_ADD + k, x, y)];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[xidx(A, k * 9 + i, x, y)] = in[xidx(A, k * 9 + i, x, y)] + a;
+    }
+}
+
+// no pending addition (before the first step of a run)
+__global__ __launch_bounds__(NTHREADS) void k_adj_clear_add(AdjPar A)
+{
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    if (x >= A.nx || y >= A.ny) return;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) A.scr[sidx(A, SCR_ADD + k, x, y)] = 0.0f;
 }
 
 // ---------------------------------------------------------------- objectives
@@ -556,6 +583,15 @@ hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st)
     const int n = nblk(A) * NPART;
     k_adj_zero<<<(n + 255) / 256, 256, 0, st>>>(A, n);
     LAUNCH_CHECK();
+    k_adj_clear_add<<<agrid(A), NTHREADS, 0, st>>>(A);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_combine(const AdjPar &A, const float *in, float *out, hipStream_t st)
+{
+    k_adj_combine<<<agrid(A), NTHREADS, 0, st>>>(A, in, out);
+    LAUNCH_CHECK();
     return hipSuccess;
 }
 
@@ -566,7 +602,7 @@ hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *lam
     LAUNCH_CHECK();
     k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam);
     LAUNCH_CHECK();
-    k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam);
+    k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -583,6 +619,7 @@ hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam
 {
     hipError_t e = launch_adjoint_zero(A, st);
     if (e == hipSuccess) e = launch_adjoint_body(A, f, lam_next, lam, st);
+    if (e == hipSuccess) e = launch_adjoint_combine(A, lam, lam, st);
     if (e == hipSuccess) e = launch_adjoint_final(A, grad, st);
     return e;
 }
@@ -597,7 +634,9 @@ hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, fl
     } else if (which == 1) {
         k_adj_local<1><<<agrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
         LAUNCH_CHECK();
-        k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam);
+        k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
+        LAUNCH_CHECK();
+        k_adj_combine<<<agrid(A), NTHREADS, 0, st>>>(A, lam, lam);
     } else {
         k_obj_lin<<<agrid(A), NTHREADS, 0, st>>>(A, f, lam, which);
     }
@@ -631,7 +670,7 @@ hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const f
     case 0: k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f); break;
     // (the timed local pass accumulates into its partial slots; cleared before use)
     case 1: k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
-    case 2: k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A, lam); break;
+    case 2: k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A); break;
     default: k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad); break;
     }
     LAUNCH_CHECK();

@@ -857,8 +857,8 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
         std::swap(cur, nxt);
     }
     if (e == hipSuccess) e = launch_adjoint_final(A, grad_dev, st);
-    if (e == hipSuccess && cur != lam_dev)
-        e = hipMemcpyAsync(lam_dev, cur, nb, hipMemcpyDeviceToDevice, st);
+    // the last step's pending addition, into lam_dev
+    if (e == hipSuccess) e = launch_adjoint_combine(A, cur, lam_dev, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint run");
     return LBM_OK;
 }

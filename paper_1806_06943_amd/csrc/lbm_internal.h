@@ -49,10 +49,12 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t 
 // ------------------------------------------------------------------ adjoint
 // Scratch planes of the instance's field region used by the adjoint passes:
 // density deviations (2), force adjoints [k][d] (4), then FP64 block partials
-// (NPART per 64 x 4 tile) followed by NPART final sums.
+// (NPART per 64 x 4 tile, a small part of one plane) followed by NPART final
+// sums, and the force transpose's addition to every lam_{k,i} of a node (2).
 constexpr int SCR_RDEV = 0;
 constexpr int SCR_FBAR = 2;
 constexpr int SCR_PART = 6;
+constexpr int SCR_ADD = 7;
 constexpr int NPART = 8;
 
 // Parameters of one instance for the adjoint kernels (passed by value).
@@ -74,10 +76,15 @@ struct AdjPar {
 
 hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam_next, float *lam,
                                double *grad, hipStream_t st);
-// pieces of a run of adjoint steps: clear the partials, one step, final sums
+// Pieces of a run of adjoint steps: clear the partials and the pending
+// addition, one step, final sums.  Between the steps of a run lam is held as
+// the local part in the caller's buffer plus a pending per-component
+// addition in scratch; launch_adjoint_combine folds it in (out = in + add,
+// in place allowed).
 hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st);
 hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *lam_next, float *lam,
                                hipStream_t st);
+hipError_t launch_adjoint_combine(const AdjPar &A, const float *in, float *out, hipStream_t st);
 hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st);
 hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, float *lam,
                                   hipStream_t st);
