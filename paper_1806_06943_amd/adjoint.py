@@ -9,14 +9,17 @@ pass keeps the state at the start of each window of steps; the backward pass
 re-runs each window forward from its checkpoint, storing its states, and
 applies the library's adjoint step (``lbm_adjoint_step``) backwards through
 the window.  The re-run of the window before runs meanwhile, in a second
-library context on a second stream, into the other of two state stores
-(events order each store's reuse), so the two latency-bound passes overlap.
+library context on a second stream fed by a second host thread, into the
+other of two state stores (events order each store's reuse), so the two
+latency-bound passes overlap.
 Memory: one state per window boundary plus two windows of states.
 
 Argument marshalling and bookkeeping only: the step, the adjoint step and the
 objective seeds all run in the HIP library.
 """
 from __future__ import annotations
+
+import threading
 
 import numpy as np
 
@@ -94,29 +97,55 @@ class Problem:
         rec.set_theta(theta)
         # the checkpoints and the seed come from the adjoint context's stream
         rec.stream.wait_stream(adj.stream)
-        recorded = [t.cuda.Event(), t.cuda.Event()]
-        released = [None, None]  # event after the last adjoint sweep that read a store
+        nw = len(wins)
+        recorded = [t.cuda.Event() for _ in range(nw)]  # window w re-run into S[w % 2]
+        released = [t.cuda.Event() for _ in range(nw)]  # sweep of window w done with it
+        queued_rec = [threading.Event() for _ in range(nw)]
+        queued_adj = [threading.Event() for _ in range(nw)]
+        failed = []
 
-        def rerun(w):
-            # the window from its checkpoint, keeping the state before each step
-            b = w % 2
-            if released[b] is not None:
-                rec.stream.wait_event(released[b])
-            rec.set_populations(ckpts[w])
-            lbm.lbm_record(rec.ctx, 0, wins[w][1], S[b].data_ptr())
-            recorded[b].record(rec.stream)
+        # One host thread per stream: a launch that blocks on a full queue
+        # (a long run of launches waiting for the other stream) then holds up
+        # only its own stream.  The order between the streams is kept on the
+        # GPU by the events; the host events only make sure that an event is
+        # recorded before the other thread queues a wait on it.
+        def rerun_all():
+            try:
+                for w in range(nw - 1, -1, -1):
+                    if w + 2 < nw:  # S[w % 2] was last read by the sweep of window w + 2
+                        queued_adj[w + 2].wait()
+                        if failed:
+                            return
+                        rec.stream.wait_event(released[w + 2])
+                    rec.set_populations(ckpts[w])
+                    lbm.lbm_record(rec.ctx, 0, wins[w][1], S[w % 2].data_ptr())
+                    recorded[w].record(rec.stream)
+                    queued_rec[w].set()
+            except BaseException as e:  # re-raised by the caller
+                failed.append(e)
+                for q in queued_rec:
+                    q.set()
 
-        if wins:
-            rerun(len(wins) - 1)
-        for w in range(len(wins) - 1, -1, -1):
-            b = w % 2
-            adj.stream.wait_event(recorded[b])
-            lbm.lbm_adjoint_run(adj.ctx, 0, wins[w][1], S[b].data_ptr(), lam.data_ptr(),
-                                tmp.data_ptr(), grad.data_ptr())
-            released[b] = t.cuda.Event()
-            released[b].record(adj.stream)
-            if w > 0:
-                rerun(w - 1)
+        th = threading.Thread(target=rerun_all, daemon=True)
+        th.start()
+        try:
+            for w in range(nw - 1, -1, -1):
+                queued_rec[w].wait()
+                if failed:
+                    break
+                adj.stream.wait_event(recorded[w])
+                lbm.lbm_adjoint_run(adj.ctx, 0, wins[w][1], S[w % 2].data_ptr(), lam.data_ptr(),
+                                    tmp.data_ptr(), grad.data_ptr())
+                released[w].record(adj.stream)
+                queued_adj[w].set()
+        except BaseException as e:
+            failed.append(e)
+        finally:
+            for q in queued_adj:
+                q.set()
+            th.join()
+        if failed:
+            raise failed[0]
         g = grad.cpu().numpy() + direct
         return g, lam
 

@@ -134,7 +134,8 @@ def _main():
     import argparse
     from . import workloads as W
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--workload", default="spinodal", choices=("spinodal", "emulsion", "batched"))
+    ap.add_argument("--workload", default="spinodal",
+                    choices=("spinodal", "emulsion", "batched", "adjoint_array"))
     ap.add_argument("--widths", default="240,496,126,62,48")
     ap.add_argument("--heights", default="8:72:2", help="start:stop:step")
     ap.add_argument("--balances", default="1,2,3,4")
