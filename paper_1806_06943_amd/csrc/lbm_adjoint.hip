@@ -54,9 +54,18 @@ __device__ __forceinline__ float apsi(const AdjPar &A, float r)
 
 // D2Q9 (order 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1)
 // 7:(-1,-1) 8:(1,-1)) with weights c_i / 36
-__constant__ int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__constant__ int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__constant__ int c_op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// compile-time tables: in the unrolled direction loops every component is a
+// known 0 or +-1
+constexpr int c_ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int c_ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int c_op[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// e v for a lattice component e in {-1, 0, 1}, without a multiply (exact)
+template <class T>
+__device__ __forceinline__ T emul(int e, T v)
+{
+    return e == 0 ? T(0) : (e > 0 ? v : -v);
+}
 
 constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
 __device__ __forceinline__ float wgt(int i) { return i == 0 ? W0 : (i < 5 ? W1 : W2); }
@@ -180,11 +189,16 @@ __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile
 // MODE 0: adjoint step.  MODE 1: seed of J_Q = (1/nx) sum_x u_x.
 // Block partials: [0..4] theta, [5] J.
 template <int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *__restrict__ f,
+// three wavefronts per SIMD: 168 VGPRs (the populations and the stencil sums
+// are not held across the transpose), LDS 33 KB per block
+__global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float *__restrict__ f,
                                                         const float *__restrict__ lam_next,
                                                         float *__restrict__ lam)
 {
     __shared__ RTile T;
+    // each thread's FP64 stencil sums [k][s1x s1y s2x s2y srx sry], parked in
+    // LDS between the force recompute and the own-node terms
+    __shared__ double SS[NTHREADS][2][6];
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     stage_rho(A, x0, y0, T);
     __syncthreads();
@@ -215,10 +229,14 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
             double s1[2], s2[2], sr[2];
             sums(k, s1, s2, sr);
 #pragma unroll
-            for (int d = 0; d < 2; ++d)
+            for (int d = 0; d < 2; ++d) {
                 F[k][d] = (float)(-(double)psi[k] * ((double)A.G1[k] * s1[d] + (double)A.G2[k] * s2[d]) -
                                   (double)A.gab * (double)rho[k] * sr[d]) +
                           rho[k] * A.g[k][d];
+                SS[threadIdx.x][k][d] = s1[d];
+                SS[threadIdx.x][k][2 + d] = s2[d];
+                SS[threadIdx.x][k][4 + d] = sr[d];
+            }
         }
         float jx[2], jy[2];
 #pragma unroll
@@ -230,10 +248,10 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
         const float iD = 1.0f / D;
         const float ux = (jx[0] * A.it[0] + jx[1] * A.it[1]) * iD;
         const float uy = (jy[0] * A.it[0] + jy[1] * A.it[1]) * iD;
-        // Compiler-only barrier (no instruction): the populations and the
-        // stencil sums are read again below instead of being held in
-        // registers across the FP64 transpose, which keeps the kernel within
-        // the register budget of two wavefronts per SIMD.
+        // Compiler-only barrier (no instruction): the populations (from
+        // cache) and the stencil sums (from LDS) are read again below instead
+        // of being held in registers across the FP64 transpose, which keeps
+        // the kernel within the register budget of two wavefronts per SIMD.
         asm volatile("" ::: "memory");
 
         // The transpose is evaluated in FP64 from the FP32 linearisation point:
@@ -271,21 +289,23 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
                 R rb = 0.0, fbx = 0.0, fby = 0.0, gt = 0.0, gg = 0.0;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) {
-                    const R ex = c_ex[i], ey = c_ey[i], w = (R)wgt9[i];
-                    const R eu = ex * Ux + ey * Uy;
-                    const R eF = ex * Fx + ey * Fy;
+                    const int ex = c_ex[i], ey = c_ey[i];
+                    const R w = (R)wgt9[i];
+                    const R eu = emul(ex, Ux) + emul(ey, Uy);
+                    const R eF = emul(ex, Fx) + emul(ey, Fy);
                     const R Em1 = 3.0 * eu + 4.5 * eu * eu - 1.5 * UU;  // E - 1
                     const R ai = (R)a[k][i];
                     rb += ai * w * (1.0 + Em1);
                     const R awr = ai * w * rk * it;
-                    ubx += awr * (3.0 * ex + 9.0 * eu * ex - 3.0 * Ux);
-                    uby += awr * (3.0 * ey + 9.0 * eu * ey - 3.0 * Uy);
-                    const R gx = 3.0 * (ex - Ux) + 9.0 * eu * ex;
-                    const R gy = 3.0 * (ey - Uy) + 9.0 * eu * ey;
+                    const R eu9 = 9.0 * eu, eF9 = 9.0 * eF;
+                    ubx += awr * (emul(ex, 3.0 + eu9) - 3.0 * Ux);
+                    uby += awr * (emul(ey, 3.0 + eu9) - 3.0 * Uy);
+                    const R gx = emul(ex, 3.0 + eu9) - 3.0 * Ux;
+                    const R gy = emul(ey, 3.0 + eu9) - 3.0 * Uy;
                     fbx += ai * w * gx;
                     fby += ai * w * gy;
-                    ubx += ai * c * w * (-3.0 * Fx + 9.0 * eF * ex);
-                    uby += ai * c * w * (-3.0 * Fy + 9.0 * eF * ey);
+                    ubx += ai * c * w * (emul(ex, eF9) - 3.0 * Fx);
+                    uby += ai * c * w * (emul(ey, eF9) - 3.0 * Fy);
                     // f - feq in deviation form: dev - w (drho + rho (E - 1))
                     const R fneq = (R)f[xidx(A, k * 9 + i, x, y)] - w * ((R)drho[k] + rk * Em1);
                     gt += ai * fneq;
@@ -330,8 +350,8 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
         // own-node terms of the force transpose and the coupling gradients
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            double s1[2], s2[2], sr[2];
-            sums(k, s1, s2, sr);
+            const double *ss = SS[threadIdx.x][k];
+            const double s1[2] = {ss[0], ss[1]}, s2[2] = {ss[2], ss[3]}, sr[2] = {ss[4], ss[5]};
             const R s1F = s1[0] * Fb[k][0] + s1[1] * Fb[k][1];
             const R s2F = s2[0] * Fb[k][0] + s2[1] * Fb[k][1];
             const R srF = sr[0] * Fb[k][0] + sr[1] * Fb[k][1];
@@ -341,7 +361,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_local(AdjPar A, const float *_
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 lam[xidx(A, k * 9 + i, x, y)] =
-                    (float)((lam_a[k] * (R)a[k][i] + mbx[k] * (R)c_ex[i] + mby[k] * (R)c_ey[i] + lam_c[k]) + rown);
+                    (float)((lam_a[k] * (R)a[k][i] + emul(c_ex[i], mbx[k]) + emul(c_ey[i], mby[k]) + lam_c[k]) + rown);
             A.scr[sidx(A, SCR_FBAR + 2 * k, x, y)] = (float)Fb[k][0];
             A.scr[sidx(A, SCR_FBAR + 2 * k + 1, x, y)] = (float)Fb[k][1];
             acc[0] += -(R)psi[k] * s1F;
