@@ -42,6 +42,12 @@ __device__ __forceinline__ int64_t xidx(const AdjPar &A, int q, int x, int y)
     return ((int64_t)q * A.ny + y) * A.nx + x;  // export layout [q][y][x]
 }
 
+// dense [2][ny][nx] density deviations
+__device__ __forceinline__ int64_t didx(const AdjPar &A, int k, int x, int y)
+{
+    return ((int64_t)k * A.ny + y) * A.nx + x;
+}
+
 __device__ __forceinline__ int64_t sidx(const AdjPar &A, int plane, int x, int y)
 {
     return (int64_t)plane * A.plane + (int64_t)y * A.pitch + x;  // scratch planes
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_density(AdjPar A, const float 
         float v[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) v[i] = f[xidx(A, k * 9 + i, x, y)];
-        A.scr[sidx(A, SCR_RDEV + k, x, y)] = sum9(v);
+        A.rscr[didx(A, k, x, y)] = sum9(v);
     }
 }
 
@@ -176,7 +182,7 @@ __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile
                 p = A.psi_wall[k];
             } else {
                 const int yy = wrapi(gy, A.ny);
-                r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, gx, yy)];
+                r = A.rho_ref[k] + A.rdev[didx(A, k, gx, yy)];
                 p = apsi(A, r);
             }
             T.rho[k][ly][lx] = r;
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
             for (int i = 0; i < 9; ++i) dev[i] = f[xidx(A, k * 9 + i, x, y)];
             rho[k] = T.rho[k][cy][cx];
             psi[k] = T.psi[k][cy][cx];
-            drho[k] = A.scr[sidx(A, SCR_RDEV + k, x, y)];
+            drho[k] = A.rdev[didx(A, k, x, y)];
             mx[k] = (dev[1] - dev[3]) + (dev[5] - dev[7]) + (dev[8] - dev[6]);
             my[k] = (dev[2] - dev[4]) + (dev[5] - dev[7]) + (dev[6] - dev[8]);
             double s1[2], s2[2], sr[2];
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A)
         const int yy = ghost ? 0 : wrapi(gy, A.ny);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const float r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, gx, yy)];
+            const float r = A.rho_ref[k] + A.rdev[didx(A, k, gx, yy)];
             const float p = apsi(A, r);
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A)
         auto ry = [&](int dx, int dy) { return T.r[1 - k][1][cy + dy][cx + dx]; };
         sum9s<float>(rx, W1, W2, cx_, cy_);
         sum9s<float>(ry, W1, W2, dx_, dy_);
-        const float r = A.rho_ref[k] + A.scr[sidx(A, SCR_RDEV + k, x, y)];
+        const float r = A.rho_ref[k] + A.rdev[didx(A, k, x, y)];
         add[k] = psibar * expf(-r * A.inv_rho0) + A.gab * (cx_ + dy_);
         (void)ay;
         (void)bx;
@@ -491,8 +497,8 @@ __global__ __launch_bounds__(NTHREADS) void k_obj_dp_sums(AdjPar A)
     const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
     double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (x < A.nx && y < A.ny) {
-        const float ra = A.rho_ref[0] + A.scr[sidx(A, SCR_RDEV, x, y)];
-        const float rb = A.rho_ref[1] + A.scr[sidx(A, SCR_RDEV + 1, x, y)];
+        const float ra = A.rho_ref[0] + A.rdev[didx(A, 0, x, y)];
+        const float rb = A.rho_ref[1] + A.rdev[didx(A, 1, x, y)];
         const float pa = apsi(A, ra), pb = apsi(A, rb);
         const float pr = bulk_pressure(A, ra, rb, pa, pb);
         const float phi = (ra - rb) / (ra + rb);
@@ -518,8 +524,8 @@ __global__ __launch_bounds__(NTHREADS) void k_obj_dp_seed(AdjPar A, float *__res
     const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
     const int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
     if (x >= A.nx || y >= A.ny) return;
-    const float ra = A.rho_ref[0] + A.scr[sidx(A, SCR_RDEV, x, y)];
-    const float rb = A.rho_ref[1] + A.scr[sidx(A, SCR_RDEV + 1, x, y)];
+    const float ra = A.rho_ref[0] + A.rdev[didx(A, 0, x, y)];
+    const float rb = A.rho_ref[1] + A.rdev[didx(A, 1, x, y)];
     const float pa = apsi(A, ra), pb = apsi(A, rb);
     const float pr = bulk_pressure(A, ra, rb, pa, pb);
     const float s = ra + rb, is2 = 1.0f / (s * s);
@@ -615,14 +621,45 @@ hipError_t launch_adjoint_combine(const AdjPar &A, const float *in, float *out, 
     return hipSuccess;
 }
 
-hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *lam_next, float *lam,
-                               hipStream_t st)
+hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rdev,
+                               const float *lam_next, float *lam, hipStream_t st)
 {
-    k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f);
+    AdjPar B = A;
+    if (rdev) {
+        B.rdev = rdev;
+    } else {
+        k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f);
+        LAUNCH_CHECK();
+        B.rdev = A.rscr;
+    }
+    k_adj_local<0><<<agrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
     LAUNCH_CHECK();
-    k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam);
+    k_adj_force<<<agrid(B), NTHREADS, 0, st>>>(B);
     LAUNCH_CHECK();
-    k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
+    return hipSuccess;
+}
+
+namespace {
+// dense density deviations of one instance's state in buffer par
+__global__ __launch_bounds__(NTHREADS) void k_rec_density(const KInst *__restrict__ insts,
+                                                          const int4 *__restrict__ tiles, int inst,
+                                                          int par, float *__restrict__ out)
+{
+    const int4 t = tiles[blockIdx.x];
+    if (t.x != inst) return;
+    const KInst &P = insts[t.x];
+    const int x = t.y + (int)(threadIdx.x % TX);
+    const int y = t.z + (int)(threadIdx.x / TX);
+    if (x >= P.nx || y >= P.ny) return;
+    const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
+    out[n] = P.rho[par][ridx(P, 0, x, y)];
+    out[N + n] = P.rho[par][ridx(P, 1, x, y)];
+}
+}  // namespace
+
+hipError_t launch_record_density(const Dev &d, int inst, int par, float *out, hipStream_t st)
+{
+    k_rec_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, inst, par, out);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -638,7 +675,7 @@ hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam
                                double *grad, hipStream_t st)
 {
     hipError_t e = launch_adjoint_zero(A, st);
-    if (e == hipSuccess) e = launch_adjoint_body(A, f, lam_next, lam, st);
+    if (e == hipSuccess) e = launch_adjoint_body(A, f, nullptr, lam_next, lam, st);
     if (e == hipSuccess) e = launch_adjoint_combine(A, lam, lam, st);
     if (e == hipSuccess) e = launch_adjoint_final(A, grad, st);
     return e;

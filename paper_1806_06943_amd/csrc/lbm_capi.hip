@@ -758,6 +758,8 @@ static AdjPar adj_par(const lbm_ctx *ctx, int inst)
     A.inv_rho0 = K.inv_rho0;
     A.qscale = (float)(1.0 / p.nx);
     A.scr = K.fld;
+    A.rscr = K.fld + (int64_t)SCR_RDEV * K.plane;  // dense: 2 nx ny <= 2 planes
+    A.rdev = A.rscr;
     A.part = (double *)(K.fld + (int64_t)SCR_PART * K.plane);
     A.res = A.part + (int64_t)adjoint_blocks(p.nx, p.ny) * NPART;
     return A;
@@ -818,10 +820,13 @@ int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
     if (rc) return rc;
     if (nsteps < 0 || (nsteps > 0 && !f_store_dev)) return fail(ctx, LBM_EINVAL, "bad arguments");
     const lbm_params &p = ctx->params[inst];
-    const int64_t N = (int64_t)18 * p.nx * p.ny;
+    const int64_t N = (int64_t)p.nx * p.ny, S = (int64_t)LBM_RECORD_PLANES * N;
     for (int64_t j = 0; j < nsteps; ++j) {
-        hipError_t e = launch_export(ctx->dev, inst, ctx->par, f_store_dev + j * N, ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "export kernel");
+        hipError_t e = launch_export(ctx->dev, inst, ctx->par, f_store_dev + j * S, ctx->stream);
+        if (e == hipSuccess)
+            e = launch_record_density(ctx->dev, inst, ctx->par, f_store_dev + j * S + 18 * N,
+                                      ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "export kernels");
         e = launch_step(ctx->dev, ctx->par, ctx->stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
         ctx->par ^= 1;
@@ -841,11 +846,11 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     if (nsteps < 0 || !lam_dev || !tmp_dev || (nsteps > 0 && !f_store_dev))
         return fail(ctx, LBM_EINVAL, "bad arguments");
     const lbm_params &p = ctx->params[inst];
-    const int64_t N = (int64_t)18 * p.nx * p.ny;
-    const uint64_t nb = (uint64_t)N * sizeof(float);
+    const int64_t N = (int64_t)p.nx * p.ny, S = (int64_t)LBM_RECORD_PLANES * N;
+    const uint64_t nb = (uint64_t)18 * N * sizeof(float), ns = (uint64_t)S * sizeof(float);
     if (overlaps(lam_dev, nb, tmp_dev, nb)) return fail(ctx, LBM_EINVAL, "lam and tmp overlap");
-    if (nsteps > 0 && (overlaps(lam_dev, nb, f_store_dev, nb * nsteps) ||
-                       overlaps(tmp_dev, nb, f_store_dev, nb * nsteps)))
+    if (nsteps > 0 && (overlaps(lam_dev, nb, f_store_dev, ns * nsteps) ||
+                       overlaps(tmp_dev, nb, f_store_dev, ns * nsteps)))
         return fail(ctx, LBM_EINVAL, "lam or tmp overlaps the state store");
     if (nsteps == 0) return LBM_OK;
     const AdjPar A = adj_par(ctx, inst);
@@ -853,7 +858,7 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     hipError_t e = launch_adjoint_zero(A, st);
     float *cur = lam_dev, *nxt = tmp_dev;
     for (int64_t j = nsteps - 1; j >= 0 && e == hipSuccess; --j) {
-        e = launch_adjoint_body(A, f_store_dev + j * N, cur, nxt, st);
+        e = launch_adjoint_body(A, f_store_dev + j * S, f_store_dev + j * S + 18 * N, cur, nxt, st);
         std::swap(cur, nxt);
     }
     if (e == hipSuccess) e = launch_adjoint_final(A, grad_dev, st);

@@ -31,6 +31,8 @@ LBM_OBJ_MASS_A = 4
 OBJECTIVES = {"dp": LBM_OBJ_DP, "Q": LBM_OBJ_Q, "momA": LBM_OBJ_MOM_A, "mom": LBM_OBJ_MOM,
               "massA": LBM_OBJ_MASS_A}
 THETA_NAMES = ("G1", "G2", "G_AB", "tau_A", "tau_B")
+# planes of nx*ny floats per state that lbm_record stores (18 populations, 2 densities)
+LBM_RECORD_PLANES = 20
 
 
 class lbm_params(ctypes.Structure):

@@ -25,6 +25,16 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
+def test_binding_constants_match_the_header():
+    """Every #define of include/lbm.h that the binding mirrors has the same value."""
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(LBM_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text)}
+    mirrored = [n for n in defs if hasattr(lbm, n)]
+    assert "LBM_RECORD_PLANES" in mirrored and "LBM_OBJ_Q" in mirrored, sorted(defs)
+    for n in mirrored:
+        assert getattr(lbm, n) == defs[n], n
+
+
 def _ok_params(**kw):
     base = dict(nx=16, ny=8, G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.6))
     base.update(kw)
