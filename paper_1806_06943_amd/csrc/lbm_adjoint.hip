@@ -9,9 +9,10 @@
 //
 // Buffers are the caller's, in the population export layout [2][9][ny][nx]
 // (FP32 deviations f - w_i rho_ref for the state; plain FP32 for lam).  One
-// adjoint step is three passes over 64 x 4 tiles:
+// adjoint step is up to three passes over 64 x 4 tiles:
 //   k_adj_density  density deviations of f (rounded as the forward step's)
-//                  into scratch plane pair rdev;
+//                  into a dense scratch array (a recorded state brings the
+//                  step's own densities instead, bitwise the same);
 //   k_adj_local    per node: recompute rho, psi, the stencil sums of Eqs. 8
 //                  and 9 (LDS tile with a halo of 2), F, j, u^eq; gather
 //                  lam*_{k,i}(x) = lam_next_{k,i}(x + e_i) (transpose of
@@ -21,11 +22,13 @@
 //                  neighbour terms); accumulate the theta terms in FP64;
 //   k_adj_force    per node: gather the neighbour terms of the transposed
 //                  force stencils from psi Fbar and rho Fbar of the 5 x 5
-//                  neighbourhood (LDS tile) and add the density adjoint to
-//                  all nine directions of lam;
+//                  neighbourhood (LDS tile); their sum adds the same density
+//                  adjoint to all nine lam_{k,i} of a component, so it is
+//                  kept as one pending value per node and component, which
+//                  the next step's gather (or k_adj_combine) adds;
 // followed by a fixed-order FP64 reduction of the per-block theta partials.
-// Scratch (densities, Fbar, block partials) lives in the instance's field
-// planes of the workspace.
+// Scratch (densities, Fbar, block partials, the pending additions) lives in
+// the instance's field planes of the workspace.
 #include <stdint.h>
 
 #include "lbm_internal.h"

@@ -53,8 +53,8 @@ enum FieldPlane { FLD_RHOA = 0, FLD_RHOB, FLD_UX, FLD_UY, FLD_PB, FLD_MX, FLD_MY
 
 // Launch parameters of one instance (device copy lives in the workspace).
 struct KInst {
-    float *f[2];           // population buffers f[y][q][x], paired with rho[]
-    float *rho[2];         // density-deviation buffers rho[y][k][x]
+    float *f[2];           // population buffers (packed rows, see fidx), paired with rho[]
+    float *rho[2];         // density-deviation buffers rho[y][x][k]
     float *fld;            // field scratch planes [NFLD][ny][pitch]
     int64_t plane;         // floats between consecutive field planes
     int32_t nx, ny, pitch, walls;
