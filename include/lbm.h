@@ -241,25 +241,24 @@ int32_t lbm_get_workgroups(const lbm_ctx *ctx);
 int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
                      float *lam_out_dev, double *grad_dev);
 
-/* Floats per recorded state, in units of nx*ny: the 18 populations in the
- * lbm_get_populations layout [2][9][ny][nx], then the 2 density deviations
- * [2][ny][nx] (sum_i f_i - rho_ref of each component, FP32 rounded once, as
- * the step computed them). */
-#define LBM_RECORD_PLANES 20
+/* Floats per state that lbm_record stores for instance inst: the state in
+ * the library's own (opaque, padded) layout, populations and their density
+ * deviations.  -1 for a bad context or instance. */
+int64_t lbm_record_floats(const lbm_ctx *ctx, int32_t inst);
 
-/* Forward run that keeps its states, for checkpoint-recompute: for
- * j = 0..nsteps-1, writes the state of instance inst (LBM_RECORD_PLANES
- * planes) into f_store_dev + j*LBM_RECORD_PLANES*nx*ny, then advances the
- * context by one step (every instance).  f_store_dev holds nsteps states.
- * Asynchronous. */
+/* Forward run that keeps its states, for checkpoint-recompute: stores the
+ * state of instance inst before each of nsteps steps, state j at
+ * f_store_dev + j*lbm_record_floats(ctx, inst), while advancing the context
+ * by nsteps steps (every instance).  The steps write these states in place
+ * (no copies beyond the first state).  Asynchronous. */
 int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev);
 
 /* nsteps adjoint steps back through a recorded window: on entry lam_dev holds
  * dJ/df(t0 + nsteps), on return dJ/df(t0); f_store_dev holds the states
  * f(t0 + j), j = 0..nsteps-1, as lbm_record writes them (the recorded
  * densities spare the adjoint its own density pass).  lam_dev and tmp_dev
- * are buffers of one population state (18*nx*ny floats); neither may overlap
- * the store or each other.
+ * are buffers of one population state in the lbm_get_populations layout
+ * (18*nx*ny floats); neither may overlap the store or each other.
  * grad_dev[0..4] (device FP64, may be NULL) += the theta-gradient of the
  * window, reduced once in a fixed order.  Asynchronous. */
 int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_store_dev,

@@ -87,7 +87,7 @@ class Problem:
         self.sim.set_theta(theta)
         m = min(self.window, max(self.steps, 1))
         if self._store is None or self._store.shape[1] < m:
-            self._store = t.empty((2, m, lbm.LBM_RECORD_PLANES) + self.shape[2:], dtype=t.float32,
+            self._store = t.empty((2, m, lbm.lbm_record_floats(self.rec.ctx, 0)), dtype=t.float32,
                                   device=self.sim.device)
         S = self._store
         grad = t.zeros(5, dtype=t.float64, device=self.sim.device)

@@ -7,12 +7,14 @@
 // (dPhi/dtheta)^T lam_next to a gradient, theta = (G1, G2, G_AB, tau_A,
 // tau_B) with G1 and G2 moving both components together.
 //
-// Buffers are the caller's, in the population export layout [2][9][ny][nx]
-// (FP32 deviations f - w_i rho_ref for the state; plain FP32 for lam).  One
+// The state (FP32 deviations f - w_i rho_ref, and its density deviations) is
+// read in the library's packed layout: a recorded window's slots, or the
+// instance's spare buffer into which the entry points import a caller's
+// state.  lam is the caller's, in the export layout [2][9][ny][nx].  One
 // adjoint step is up to three passes over 64 x 4 tiles:
 //   k_adj_density  density deviations of f (rounded as the forward step's)
-//                  into a dense scratch array (a recorded state brings the
-//                  step's own densities instead, bitwise the same);
+//                  into scratch (a recorded state brings the densities the
+//                  step wrote, bitwise the same);
 //   k_adj_local    per node: recompute rho, psi, the stencil sums of Eqs. 8
 //                  and 9 (LDS tile with a halo of 2), F, j, u^eq; gather
 //                  lam*_{k,i}(x) = lam_next_{k,i}(x + e_i) (transpose of
@@ -45,10 +47,16 @@ __device__ __forceinline__ int64_t xidx(const AdjPar &A, int q, int x, int y)
     return ((int64_t)q * A.ny + y) * A.nx + x;  // export layout [q][y][x]
 }
 
-// dense [2][ny][nx] density deviations
+// the library's packed state layout (pitch A.pitch): population q = 9 k + i
+// in four float4 planes and one float2 plane per row, densities rho[y][x][k]
+__device__ __forceinline__ int64_t pidx(const AdjPar &A, int q, int x, int y)
+{
+    return ((int64_t)y * 18 + (q & ~3)) * A.pitch + (int64_t)x * (q < 16 ? 4 : 2) + (q & 3);
+}
+
 __device__ __forceinline__ int64_t didx(const AdjPar &A, int k, int x, int y)
 {
-    return ((int64_t)k * A.ny + y) * A.nx + x;
+    return ((int64_t)y * A.pitch + x) * 2 + k;
 }
 
 __device__ __forceinline__ int64_t sidx(const AdjPar &A, int plane, int x, int y)
@@ -159,7 +167,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_density(AdjPar A, const float 
     for (int k = 0; k < 2; ++k) {
         float v[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = f[xidx(A, k * 9 + i, x, y)];
+        for (int i = 0; i < 9; ++i) v[i] = f[pidx(A, k * 9 + i, x, y)];
         A.rscr[didx(A, k, x, y)] = sum9(v);
     }
 }
@@ -229,7 +237,7 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
         for (int k = 0; k < 2; ++k) {
             float dev[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dev[i] = f[xidx(A, k * 9 + i, x, y)];
+            for (int i = 0; i < 9; ++i) dev[i] = f[pidx(A, k * 9 + i, x, y)];
             rho[k] = T.rho[k][cy][cx];
             psi[k] = T.psi[k][cy][cx];
             drho[k] = A.rdev[didx(A, k, x, y)];
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
                     ubx += ai * c * w * (emul(ex, eF9) - 3.0 * Fx);
                     uby += ai * c * w * (emul(ey, eF9) - 3.0 * Fy);
                     // f - feq in deviation form: dev - w (drho + rho (E - 1))
-                    const R fneq = (R)f[xidx(A, k * 9 + i, x, y)] - w * ((R)drho[k] + rk * Em1);
+                    const R fneq = (R)f[pidx(A, k * 9 + i, x, y)] - w * ((R)drho[k] + rk * Em1);
                     gt += ai * fneq;
                     gg += ai * w * (gx * Fx + gy * Fy);
                 }
@@ -565,7 +573,7 @@ __global__ __launch_bounds__(NTHREADS) void k_obj_lin(AdjPar A, const float *__r
             for (int i = 0; i < 9; ++i) {
                 const float c = which == 4 ? (k == 0 ? 1.0f : 0.0f)
                                            : (which == 2 && k == 1 ? 0.0f : (float)c_ex[i]);
-                const float fi = f[xidx(A, k * 9 + i, x, y)] + wgt(i) * A.rho_ref[k];
+                const float fi = f[pidx(A, k * 9 + i, x, y)] + wgt(i) * A.rho_ref[k];
                 s += (double)c * (double)fi;
                 if (lam) lam[xidx(A, k * 9 + i, x, y)] = c;
             }
@@ -642,30 +650,6 @@ hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rde
     return hipSuccess;
 }
 
-namespace {
-// dense density deviations of one instance's state in buffer par
-__global__ __launch_bounds__(NTHREADS) void k_rec_density(const KInst *__restrict__ insts,
-                                                          const int4 *__restrict__ tiles, int inst,
-                                                          int par, float *__restrict__ out)
-{
-    const int4 t = tiles[blockIdx.x];
-    if (t.x != inst) return;
-    const KInst &P = insts[t.x];
-    const int x = t.y + (int)(threadIdx.x % TX);
-    const int y = t.z + (int)(threadIdx.x / TX);
-    if (x >= P.nx || y >= P.ny) return;
-    const int64_t N = (int64_t)P.nx * P.ny, n = (int64_t)y * P.nx + x;
-    out[n] = P.rho[par][ridx(P, 0, x, y)];
-    out[N + n] = P.rho[par][ridx(P, 1, x, y)];
-}
-}  // namespace
-
-hipError_t launch_record_density(const Dev &d, int inst, int par, float *out, hipStream_t st)
-{
-    k_rec_density<<<d.ntiles, NTHREADS, 0, st>>>(d.insts, d.tiles, inst, par, out);
-    LAUNCH_CHECK();
-    return hipSuccess;
-}
 
 hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st)
 {

@@ -758,7 +758,7 @@ static AdjPar adj_par(const lbm_ctx *ctx, int inst)
     A.inv_rho0 = K.inv_rho0;
     A.qscale = (float)(1.0 / p.nx);
     A.scr = K.fld;
-    A.rscr = K.fld + (int64_t)SCR_RDEV * K.plane;  // dense: 2 nx ny <= 2 planes
+    A.rscr = K.fld + (int64_t)SCR_RDEV * K.plane;  // one packed density buffer <= 2 planes
     A.rdev = A.rscr;
     A.part = (double *)(K.fld + (int64_t)SCR_PART * K.plane);
     A.res = A.part + (int64_t)adjoint_blocks(p.nx, p.ny) * NPART;
@@ -770,6 +770,15 @@ static bool overlaps(const void *a, uint64_t na, const void *b, uint64_t nb)
 {
     const char *x = (const char *)a, *y = (const char *)b;
     return x < y + nb && y < x + na;
+}
+
+// The caller's state f_dev (lbm_get_populations layout) in the packed layout
+// of the adjoint kernels, in the instance's spare population buffer f[par ^ 1]
+// (free between steps: the next step overwrites it).
+static const float *packed_state(lbm_ctx *ctx, int inst, const float *f_dev, hipError_t *e)
+{
+    *e = launch_import(ctx->dev, inst, ctx->par ^ 1, f_dev, ctx->stream);
+    return ctx->hinst[inst].f[ctx->par ^ 1];
 }
 
 int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
@@ -785,8 +794,10 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float
     const uint64_t nb = (uint64_t)18 * p.nx * p.ny * sizeof(float);
     if (overlaps(lam_out_dev, nb, lam_in_dev, nb) || overlaps(lam_out_dev, nb, f_dev, nb))
         return fail(ctx, LBM_EINVAL, "lam_out must not overlap f or lam_in");
-    hipError_t e = launch_adjoint_step(adj_par(ctx, inst), f_dev, lam_in_dev, lam_out_dev, grad_dev,
-                                       ctx->stream);
+    hipError_t e;
+    const float *fp = packed_state(ctx, inst, f_dev, &e);
+    if (e == hipSuccess)
+        e = launch_adjoint_step(adj_par(ctx, inst), fp, lam_in_dev, lam_out_dev, grad_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint kernels");
     return LBM_OK;
 }
@@ -813,21 +824,36 @@ int lbm_pressure(lbm_ctx *ctx, int32_t inst, float *P_dev, double *line_tension)
     return LBM_OK;
 }
 
+int64_t lbm_record_floats(const lbm_ctx *ctx, int32_t inst)
+{
+    if (!ctx || inst < 0 || inst >= ctx->n_inst) return -1;
+    const InstLayout &L = ctx->layout.inst[inst];
+    return L.fsize + L.rsize;
+}
+
 int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
 {
     CTX_CHECK(ctx);
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
     if (nsteps < 0 || (nsteps > 0 && !f_store_dev)) return fail(ctx, LBM_EINVAL, "bad arguments");
-    const lbm_params &p = ctx->params[inst];
-    const int64_t N = (int64_t)p.nx * p.ny, S = (int64_t)LBM_RECORD_PLANES * N;
+    if (nsteps == 0) return LBM_OK;
+    const InstLayout &L = ctx->layout.inst[inst];
+    const KInst &K = ctx->hinst[inst];
+    const int64_t S = L.fsize + L.rsize;
+    hipStream_t st = ctx->stream;
+    // slot 0 = the current state; step j reads slot j and writes slot j + 1
+    // (the last step the context's own buffers, so the context advances)
+    HIP_TRY(ctx, hipMemcpyAsync(f_store_dev, K.f[ctx->par], L.fsize * sizeof(float),
+                                hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(f_store_dev + L.fsize, K.rho[ctx->par], L.rsize * sizeof(float),
+                                hipMemcpyDeviceToDevice, st));
     for (int64_t j = 0; j < nsteps; ++j) {
-        hipError_t e = launch_export(ctx->dev, inst, ctx->par, f_store_dev + j * S, ctx->stream);
-        if (e == hipSuccess)
-            e = launch_record_density(ctx->dev, inst, ctx->par, f_store_dev + j * S + 18 * N,
-                                      ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "export kernels");
-        e = launch_step(ctx->dev, ctx->par, ctx->stream);
+        float *cur = f_store_dev + j * S, *nxt = f_store_dev + (j + 1) * S;
+        const bool last = j + 1 == nsteps;
+        const StepOvr o{inst, cur, cur + L.fsize, last ? K.f[ctx->par ^ 1] : nxt,
+                        last ? K.rho[ctx->par ^ 1] : nxt + L.fsize};
+        hipError_t e = launch_step_ovr(ctx->dev, ctx->par, o, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
         ctx->par ^= 1;
     }
@@ -846,7 +872,8 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     if (nsteps < 0 || !lam_dev || !tmp_dev || (nsteps > 0 && !f_store_dev))
         return fail(ctx, LBM_EINVAL, "bad arguments");
     const lbm_params &p = ctx->params[inst];
-    const int64_t N = (int64_t)p.nx * p.ny, S = (int64_t)LBM_RECORD_PLANES * N;
+    const InstLayout &L = ctx->layout.inst[inst];
+    const int64_t N = (int64_t)p.nx * p.ny, S = L.fsize + L.rsize;
     const uint64_t nb = (uint64_t)18 * N * sizeof(float), ns = (uint64_t)S * sizeof(float);
     if (overlaps(lam_dev, nb, tmp_dev, nb)) return fail(ctx, LBM_EINVAL, "lam and tmp overlap");
     if (nsteps > 0 && (overlaps(lam_dev, nb, f_store_dev, ns * nsteps) ||
@@ -858,7 +885,7 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     hipError_t e = launch_adjoint_zero(A, st);
     float *cur = lam_dev, *nxt = tmp_dev;
     for (int64_t j = nsteps - 1; j >= 0 && e == hipSuccess; --j) {
-        e = launch_adjoint_body(A, f_store_dev + j * S, f_store_dev + j * S + 18 * N, cur, nxt, st);
+        e = launch_adjoint_body(A, f_store_dev + j * S, f_store_dev + j * S + L.fsize, cur, nxt, st);
         std::swap(cur, nxt);
     }
     if (e == hipSuccess) e = launch_adjoint_final(A, grad_dev, st);
@@ -887,7 +914,9 @@ int lbm_adjoint_seed(lbm_ctx *ctx, int32_t inst, int32_t objective, const float 
         return fail(ctx, LBM_EINVAL, "lam_dev must not overlap f_dev");
     const AdjPar A = adj_par(ctx, inst);
     hipStream_t st = ctx->stream;
-    hipError_t e = launch_objective_pass1(A, objective, f_dev, lam_dev, st);
+    hipError_t e;
+    const float *fp = packed_state(ctx, inst, f_dev, &e);
+    if (e == hipSuccess) e = launch_objective_pass1(A, objective, fp, lam_dev, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "objective kernels");
     double res[NPART];
     HIP_TRY(ctx, hipMemcpyAsync(res, A.res, sizeof res, hipMemcpyDeviceToHost, st));
@@ -954,16 +983,19 @@ int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const fl
     const AdjPar A = adj_par(ctx, inst);
     hipStream_t st = ctx->stream;
     *n_kernels = N_ADJ_KERNELS;
+    hipError_t ei;
+    const float *fp = packed_state(ctx, inst, f_dev, &ei);
+    if (ei != hipSuccess) return hip_fail(ctx, ei, "import");
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     rc = LBM_OK;
     for (int j = 0; j < N_ADJ_KERNELS && j < max_k && rc == LBM_OK; ++j) {
         hipError_t e = launch_adjoint_zero(A, st);
-        if (e == hipSuccess) e = launch_adjoint_kernel(A, j, f_dev, lam_in_dev, lam_out_dev, grad_dev, st);
+        if (e == hipSuccess) e = launch_adjoint_kernel(A, j, fp, lam_in_dev, lam_out_dev, grad_dev, st);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int r = 0; r < nrep && e == hipSuccess; ++r)
-            e = launch_adjoint_kernel(A, j, f_dev, lam_in_dev, lam_out_dev, grad_dev, st);
+            e = launch_adjoint_kernel(A, j, fp, lam_in_dev, lam_out_dev, grad_dev, st);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.f;

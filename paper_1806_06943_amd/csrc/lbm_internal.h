@@ -37,6 +37,14 @@ constexpr int MAX_STRIP_COLS = 8 * 64 - 2;
 
 hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
 hipError_t launch_step(const Dev &d, int par, hipStream_t st);
+// Buffers that replace one instance's ping-pong pair for one launch of the
+// fused step (a window recorded in place); inst < 0: none.
+struct StepOvr {
+    int inst;
+    const float *fin, *rin;
+    float *fout, *rout;
+};
+hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t st);
 hipError_t launch_density(const Dev &d, int par, hipStream_t st);
 hipError_t launch_fields(const Dev &d, int par, hipStream_t st);
 hipError_t launch_fields_out(const Dev &d, int inst, float *rho, float *u, hipStream_t st);
@@ -48,7 +56,7 @@ hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t 
 
 // ------------------------------------------------------------------ adjoint
 // Scratch planes of the instance's field region used by the adjoint passes:
-// density deviations (the first 2 planes, holding a dense [2][ny][nx] array),
+// density deviations (the first 2 planes, holding one packed density buffer),
 // force adjoints [k][d] (4), then FP64 block partials
 // (NPART per 64 x 4 tile, a small part of one plane) followed by NPART final
 // sums, and the force transpose's addition to every lam_{k,i} of a node (2).
@@ -71,8 +79,8 @@ struct AdjPar {
     float rho0, inv_rho0;
     float qscale;           // 1 / nx (flow-rate objective)
     float *scr;             // scratch planes
-    float *rscr;            // dense [2][ny][nx] density deviations written by k_adj_density
-    const float *rdev;      // dense [2][ny][nx] density deviations of the state being transposed
+    float *rscr;            // density deviations written by k_adj_density (packed, rho[y][x][k])
+    const float *rdev;      // density deviations of the state being transposed (packed)
     double *part;           // [blocks][NPART]
     double *res;            // [NPART]
 };
@@ -85,11 +93,10 @@ hipError_t launch_adjoint_step(const AdjPar &A, const float *f, const float *lam
 // addition in scratch; launch_adjoint_combine folds it in (out = in + add,
 // in place allowed).
 hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st);
-// rdev: the state's dense density deviations (recorded), or NULL to compute them
+// f: the state's populations in the library's packed layout; rdev: its
+// density deviations (packed, recorded), or NULL to compute them
 hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rdev,
                                const float *lam_next, float *lam, hipStream_t st);
-// dense density deviations of instance inst's current state (for lbm_record)
-hipError_t launch_record_density(const Dev &d, int inst, int par, float *out, hipStream_t st);
 hipError_t launch_adjoint_combine(const AdjPar &A, const float *in, float *out, hipStream_t st);
 hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st);
 hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, float *lam,

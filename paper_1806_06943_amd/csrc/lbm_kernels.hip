@@ -174,9 +174,8 @@ struct RingAccW {
 // outstanding stores.  One-wave strips fit in 128.
 template <int NW, int FS>
 __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
-    const KInst *__restrict__ insts,
-                                                         const int4 *__restrict__ segs,
-                                                         const int *__restrict__ first, int par)
+    const KInst *__restrict__ insts, const int4 *__restrict__ segs, const int *__restrict__ first,
+    int par, StepOvr ovr)
 {
     constexpr int NL = 64 * NW;
     __shared__ RingW<NW> R;
@@ -198,10 +197,12 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
     const uint32_t pb = (uint32_t)G.pitch;        // nodes per row (with padding)
     const uint32_t frowb = 72u * pb;              // bytes per population row
     const uint32_t rrowb = 8u * pb;               // bytes per density row
-    const __amdgpu_buffer_rsrc_t fin = make_rsrc(G.f[par], (uint32_t)ny * frowb);
-    const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(G.rho[par], (uint32_t)ny * rrowb);
-    const __amdgpu_buffer_rsrc_t rout = make_rsrc(G.rho[par ^ 1], (uint32_t)ny * rrowb);
+    // the instance's ping-pong pair, or the override's buffers (same layout)
+    const bool ov = t.x == ovr.inst;
+    const __amdgpu_buffer_rsrc_t fin = make_rsrc(ov ? ovr.fin : G.f[par], (uint32_t)ny * frowb);
+    const __amdgpu_buffer_rsrc_t fout = make_rsrc(ov ? ovr.fout : G.f[par ^ 1], (uint32_t)ny * frowb);
+    const __amdgpu_buffer_rsrc_t rin = make_rsrc(ov ? ovr.rin : G.rho[par], (uint32_t)ny * rrowb);
+    const __amdgpu_buffer_rsrc_t rout = make_rsrc(ov ? ovr.rout : G.rho[par ^ 1], (uint32_t)ny * rrowb);
     const uint32_t xc = (uint32_t)wrapi(X0 - 1 + L, nx);  // collided column
     const bool outl = (L >= 1) && (L <= wo);
     // out-of-range offset: a load returns 0 without a memory request, a store
@@ -952,27 +953,32 @@ hipError_t launch_density(const Dev &d, int par, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t launch_step(const Dev &d, int par, hipStream_t st)
+hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t st)
 {
     if (d.forcing) {
         switch (d.nw) {
-        case 1: k_fused_step<1, 1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 2: k_fused_step<2, 1><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 4: k_fused_step<4, 1><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 8: k_fused_step<8, 1><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 1: k_fused_step<1, 1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 2: k_fused_step<2, 1><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 4: k_fused_step<4, 1><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 8: k_fused_step<8, 1><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (d.nw) {
-        case 1: k_fused_step<1, 0><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 2: k_fused_step<2, 0><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 4: k_fused_step<4, 0><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par); break;
-        case 8: k_fused_step<8, 0><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par); break;
+        case 1: k_fused_step<1, 0><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 2: k_fused_step<2, 0><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 4: k_fused_step<4, 0><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+        case 8: k_fused_step<8, 0><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
         default: return hipErrorInvalidValue;
         }
     }
     LAUNCH_CHECK();
     return hipSuccess;
+}
+
+hipError_t launch_step(const Dev &d, int par, hipStream_t st)
+{
+    return launch_step_ovr(d, par, StepOvr{-1, nullptr, nullptr, nullptr, nullptr}, st);
 }
 
 const char *step_kernel_name(int j)

@@ -31,8 +31,6 @@ LBM_OBJ_MASS_A = 4
 OBJECTIVES = {"dp": LBM_OBJ_DP, "Q": LBM_OBJ_Q, "momA": LBM_OBJ_MOM_A, "mom": LBM_OBJ_MOM,
               "massA": LBM_OBJ_MASS_A}
 THETA_NAMES = ("G1", "G2", "G_AB", "tau_A", "tau_B")
-# planes of nx*ny floats per state that lbm_record stores (18 populations, 2 densities)
-LBM_RECORD_PLANES = 20
 
 
 class lbm_params(ctypes.Structure):
@@ -114,6 +112,8 @@ def lib() -> ctypes.CDLL:
                                        P(ctypes.c_double), P(ctypes.c_double)]
         L.lbm_set_params.argtypes = [vp, ctypes.c_int32, P(lbm_params)]
         L.lbm_record.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp]
+        L.lbm_record_floats.argtypes = [vp, ctypes.c_int32]
+        L.lbm_record_floats.restype = ctypes.c_int64
         L.lbm_pressure.argtypes = [vp, ctypes.c_int32, vp, P(ctypes.c_double)]
         L.lbm_adjoint_run.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp]
         L.lbm_profile_adjoint.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
@@ -278,6 +278,13 @@ def lbm_pressure(ctx, inst: int, P_ptr: int, want_line_tension: bool = True):
     _check(lib().lbm_pressure(ctx, inst, ctypes.c_void_p(P_ptr),
                               ctypes.byref(lt) if want_line_tension else None), ctx)
     return float(lt.value) if want_line_tension else None
+
+
+def lbm_record_floats(ctx, inst: int) -> int:
+    n = int(lib().lbm_record_floats(ctx, inst))
+    if n < 0:
+        raise LBMError(LBM_EINVAL, "bad context or instance")
+    return n
 
 
 def lbm_record(ctx, inst: int, nsteps: int, f_store_ptr: int):

@@ -30,7 +30,7 @@ def test_binding_constants_match_the_header():
     text = open(os.path.join(ROOT, "include", "lbm.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(LBM_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text)}
     mirrored = [n for n in defs if hasattr(lbm, n)]
-    assert "LBM_RECORD_PLANES" in mirrored and "LBM_OBJ_Q" in mirrored, sorted(defs)
+    assert "LBM_FORCING_SHIFT" in mirrored and "LBM_OBJ_Q" in mirrored, sorted(defs)
     for n in mirrored:
         assert getattr(lbm, n) == defs[n], n
 
