@@ -43,14 +43,14 @@ DOMINANT = "k_fused_step"
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
 # library), per strip plan (width, height, workgroups per CU), valid only for
 # the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "c04eb1b4ac8545b8",
-                    "plans": {(240, 37, 0): (176944.0 * 2.0 * 1024, 327687.3 * 1024),
-                              (240, 38, 0): (176939.8 * 2.0 * 1024, 327685.6 * 1024),
-                              (240, 40, 0): (176890.6 * 2.0 * 1024, 327684.7 * 1024),
-                              (240, 42, 0): (176642.2 * 2.0 * 1024, 327682.2 * 1024),
-                              (510, 42, 0): (173933.3 * 2.0 * 1024, 328007.3 * 1024),
-                              (126, 46, 0): (174396.2 * 2.0 * 1024, 330748.3 * 1024),
-                              (254, 40, 0): (175367.0 * 2.0 * 1024, 329172.4 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "42b8ed9e1d32e6e1",
+                    "plans": {(240, 37, 0): (177298.7 * 2.0 * 1024, 327689.7 * 1024),
+                              (240, 38, 0): (177433.1 * 2.0 * 1024, 327687.5 * 1024),
+                              (240, 40, 0): (177410.9 * 2.0 * 1024, 327687.0 * 1024),
+                              (240, 42, 0): (177222.0 * 2.0 * 1024, 327683.3 * 1024),
+                              (510, 42, 0): (173981.5 * 2.0 * 1024, 328308.0 * 1024),
+                              (126, 46, 0): (174727.0 * 2.0 * 1024, 331175.4 * 1024),
+                              (254, 40, 0): (175528.7 * 2.0 * 1024, 329300.1 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
