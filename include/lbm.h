@@ -180,7 +180,7 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
                      int32_t *n_kernels);
 
 /* Strip height of the fused step (lattice rows one strip advances per step,
- * default 16, at least 4); selects the uniform plan (every column strip cut
+ * default 16, at least 2); selects the uniform plan (every column strip cut
  * into ceil(ny / chunk_rows) chunks, one workgroup each).  Any value gives
  * the same results bit for bit; it trades halo recomputation against
  * parallelism.  Synchronises the stream and discards captured graphs. */

@@ -16,7 +16,7 @@ namespace {
 
 constexpr int GRAPH_STEPS = 16;  // steps per captured graph (even: parity unchanged)
 constexpr uint64_t ALIGN = 256;
-constexpr int MIN_CHUNK = 4;     // smallest strip height the workspace is sized for
+constexpr int MIN_CHUNK = 2;     // smallest strip height the workspace is sized for
 constexpr int DEFAULT_CHUNK = 16;
 constexpr int MIN_WIDTH = 16;    // narrowest strip the workspace is sized for
 constexpr int DEFAULT_WIDTH = SWO;
@@ -691,7 +691,7 @@ int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
 {
     CTX_CHECK(ctx);
     if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
-        return fail(ctx, LBM_EINVAL, "chunk_rows must be in [4, 65535]");
+        return fail(ctx, LBM_EINVAL, "chunk_rows must be in [2, 65535]");
     return set_strips(ctx, chunk_rows, ctx->width, 0);
 }
 

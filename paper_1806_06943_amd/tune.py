@@ -22,8 +22,8 @@ import os
 
 from . import lbm
 
-CANDIDATES = (4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
-MIN_HEIGHT = 4  # the smallest strip height lbm_set_tiling accepts
+CANDIDATES = (2, 3, 4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
+MIN_HEIGHT = 2  # the smallest strip height lbm_set_tiling accepts
 # (output columns per strip): one wavefront per strip, balanced / aligned,
 # then strips of 2, 4 and 8 wavefronts, balanced / aligned
 WIDTHS = (62, 48, 126, 112, 254, 240, 510, 496)

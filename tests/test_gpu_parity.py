@@ -355,7 +355,7 @@ def test_strip_height_does_not_change_results(torch):
     """The strip height only moves work between wavefronts: results are bitwise equal."""
     w = W.emulsion(nx=200, ny=96, ndrop=4, radius=9, gx=1e-5)
     ref = None
-    for h in (4, 7, 16, 40, 96):
+    for h in (2, 3, 4, 7, 16, 40, 96):
         sim = lbm.Sim([lbm.workload_instance(w)])
         lbm.lbm_set_tiling(sim.ctx, h)
         assert lbm.lbm_get_tiling(sim.ctx) == h
