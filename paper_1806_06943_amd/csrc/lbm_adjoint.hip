@@ -42,26 +42,33 @@ namespace {
 constexpr int AW = TX + 2 * HALO;  // staged tile width
 constexpr int AH = TY + 2 * HALO;  // staged tile height
 
+// Element indices in 32-bit arithmetic: every instance buffer stays below
+// 2 GiB (checked at init), so no index reaches 2^31.
 __device__ __forceinline__ int64_t xidx(const AdjPar &A, int q, int x, int y)
 {
-    return ((int64_t)q * A.ny + y) * A.nx + x;  // export layout [q][y][x]
+    return (int64_t)(((uint32_t)q * (uint32_t)A.ny + (uint32_t)y) * (uint32_t)A.nx + (uint32_t)x);  // [q][y][x]
 }
 
 // the library's packed state layout (pitch A.pitch): population q = 9 k + i
 // in four float4 planes and one float2 plane per row, densities rho[y][x][k]
 __device__ __forceinline__ int64_t pidx(const AdjPar &A, int q, int x, int y)
 {
-    return ((int64_t)y * 18 + (q & ~3)) * A.pitch + (int64_t)x * (q < 16 ? 4 : 2) + (q & 3);
+    return (int64_t)(((uint32_t)y * 18u + (uint32_t)(q & ~3)) * (uint32_t)A.pitch +
+                     (uint32_t)x * (q < 16 ? 4u : 2u) + (uint32_t)(q & 3));
 }
 
 __device__ __forceinline__ int64_t didx(const AdjPar &A, int k, int x, int y)
 {
-    return ((int64_t)y * A.pitch + x) * 2 + k;
+    return (int64_t)(((uint32_t)y * (uint32_t)A.pitch + (uint32_t)x) * 2u + (uint32_t)k);
 }
+
+// periodic wrap of an index at most one period outside [0, n)
+__device__ __forceinline__ int wrap1(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 __device__ __forceinline__ int64_t sidx(const AdjPar &A, int plane, int x, int y)
 {
-    return (int64_t)plane * A.plane + (int64_t)y * A.pitch + x;  // scratch planes
+    return (int64_t)((uint32_t)plane * (uint32_t)A.plane + (uint32_t)y * (uint32_t)A.pitch +
+                     (uint32_t)x);  // scratch planes
 }
 
 __device__ __forceinline__ float apsi(const AdjPar &A, float r)
@@ -290,8 +297,8 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
             for (int i = 0; i < 9; ++i) {
                 const int yd = y + c_ey[i];
                 const bool bounce = A.walls && (yd < 0 || yd >= A.ny);
-                const int xs = bounce ? x : wrapi(x + c_ex[i], A.nx);
-                const int ys = bounce ? y : wrapi(yd, A.ny);
+                const int xs = bounce ? x : wrap1(x + c_ex[i], A.nx);
+                const int ys = bounce ? y : wrap1(yd, A.ny);
                 const int is = bounce ? c_op[i] : i;
 #pragma unroll
                 for (int k = 0; k < 2; ++k)
