@@ -191,10 +191,32 @@ def cpu_baseline(w, budget_s=15.0, steps=0):
     t0 = time.perf_counter()
     O.run(p, f, n)
     dt = time.perf_counter() - t0
-    return {"value": w.nx * w.ny * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+    cores = O.threads()
+    # the same oracle on one thread, a bounded sample of a few steps
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.run(p, f, 1)
+        t1s = time.perf_counter() - t0
+        n1 = max(1, min(10, int(0.5 * budget_s / max(t1s, 1e-6))))
+        t0 = time.perf_counter()
+        O.run(p, f, n1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(cores)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": w.nx * w.ny * n / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} steps of the {w.nx}x{w.ny} spinodal workload, FP64, "
-                      f"OpenMP over rows ({dt:.1f} s)"}
+                      f"OpenMP over rows ({dt:.1f} s)",
+            "single_thread": {"value": w.nx * w.ny * n1 / dt1 / 1e6, "unit": "MLUPS",
+                              "sample": f"{n1} steps, 1 thread ({dt1:.1f} s)"},
+            "cpu_model": model}
 
 
 def main():

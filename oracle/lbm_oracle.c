@@ -74,6 +74,16 @@ int ora_threads(void)
 #endif
 }
 
+/* threads for the following row loops (timing of the oracle on n cores) */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---- lattice tables, typed from Sec. II A (D2Q9) and Sec. II B (D2Q25) ---- */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};

@@ -94,6 +94,7 @@ def lib():
         L.ora_init.argtypes = [P, _D, _D, _D]
         L.ora_fields.argtypes = [P, _D, _D, _D, _D, _D, _D, _D]
         L.ora_threads.restype = ctypes.c_int
+        L.ora_set_threads.argtypes = [ctypes.c_int]
         L.ora_adjoint_step.argtypes = [P, _D, _D, _D, _D, _D]
         L.ora_objective.argtypes = [P, _D, ctypes.c_int, _D, _D, _D]
         L.ora_objective.restype = ctypes.c_double
@@ -104,6 +105,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads used by the oracle's row loops."""
     return int(lib().ora_threads())
+
+
+def set_threads(n: int):
+    """OpenMP threads for the following row loops (timing only)."""
+    lib().ora_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray | None):
