@@ -19,6 +19,11 @@
   meeting head-on at Ca ~ 0.3 and We ~ 15 bounce back under the present model
   at M = 1 and M = 3 (the film of B between them survives); the single-range
   model coalesces in the same collision; the original model bounces at M = 1.
+* Emulsion viscosity (Sec. III D, Eq. 20): a walled 220 x 220 channel at
+  F_b-bar = 37 and M = 1 with 5 x 5 droplets; the relative viscosity
+  Q(0) / Q(Phi) rises with Phi and stays within 10 % of the paper's fit
+  (K = 1, [eta] = 0.88) up to Phi = 0.37, and the droplet-free channel carries
+  the Poiseuille flow rate.
 
 Viscosities in Eq. 19 are the bulk-phase mixture viscosities sum_k rho_k nu_k,
 as in the oracle's pin of the same flow.
@@ -320,3 +325,66 @@ def test_droplet_collision_original_model_bounces_at_unit_ratio(torch):
     sep = [s for _, s, _ in hist]
     assert all(n == 2 for n, _, _ in hist) and all(g > 0.5 for _, _, g in hist), hist
     assert sep[-1] > min(sep) + 10.0, sep
+
+
+def emulsion_cases(L, R_list, tau=1.0, Fbar=37.0):
+    """Walled L x L channels, one per R (R = 0: no droplets), each holding 5 x 5
+    droplets of A of radius R on a square grid in the B matrix; the body force
+    F_b = Fbar 8 nu^2 / L^3 on both components (Fbar = F_b L^3 / (8 rho nu^2) as
+    in Sec. III D, rho_B = 1)."""
+    nu = (tau - 0.5) / 3.0
+    Fb = Fbar * 8.0 * nu * nu / L ** 3
+    yy, xx = np.mgrid[0:L, 0:L]
+    out = []
+    for R in R_list:
+        A = np.zeros((L, L), bool)
+        for i in range(5 if R else 0):
+            for j in range(5):
+                A |= (xx - (i + 0.5) * L / 5) ** 2 + (yy - (j + 0.5) * L / 5) ** 2 <= R * R
+        out.append((float(A.mean()), dict(nx=L, ny=L, rhoA=np.where(A, 1.0, 0.03),
+                                          rhoB=np.where(A, 0.03, 1.0), G_AB=3.0, G1=-7.4, G2=6.4,
+                                          tau=(tau, tau), walls=1, rho_wall=(0.03, 1.0),
+                                          g=((0.0, 0.0), (0.0, 0.0)))))
+    return Fb, nu, out
+
+
+def test_emulsion_relative_viscosity_follows_the_fit(torch):
+    """The droplets relax 30 000 steps at rest, then the body force drives the
+    channel for 270 000 steps (about nine decay times L^2 / (pi^2 nu) of the
+    slowest viscous mode)."""
+    import time
+    L = 220
+    Fb, nu, cases = emulsion_cases(L, (0.0, 10.0, 12.5, 15.0))
+    say("emulsion", L, "phi", [round(p, 3) for p, _ in cases])
+    sim = lbm.Sim([c for _, c in cases])
+    try:
+        t0 = time.time()
+        sim.step(30000)
+        for i in range(len(cases)):
+            p = lbm.lbm_params.from_buffer_copy(sim.params[i])
+            p.g[0][0] = Fb
+            p.g[1][0] = Fb
+            lbm.lbm_set_params(sim.ctx, i, p)
+            sim.params[i] = p
+        sim.step(270000)
+        obs, _ = sim.observables()
+        rho = [sim.fields(i)[0].cpu().numpy() for i in range(len(cases))]
+        say("emulsion steps done in", round(time.time() - t0, 1), "s")
+    finally:
+        sim.close()
+    assert all(o["finite"] for o in obs)
+    Q = [o["flow_rate"] for o in obs]
+    phi = [p for p, _ in cases]
+    mu = [Q[0] / q for q in Q]
+    demt = [(1.0 - p) ** -0.88 for p in phi]
+    say("Q", [round(q, 4) for q in Q], "mu_r", [round(m, 4) for m in mu],
+        "DEMT", [round(d, 4) for d in demt])
+    # no droplets: plane Poiseuille flow between half-way walls, Q = F_b L^3 / (12 nu)
+    # per unit density (Sec. III D defines Fbar with the matrix density)
+    q_pois = Fb * L ** 3 / (12.0 * nu)
+    assert abs(Q[0] / q_pois - 1.0) < 0.01, (Q[0], q_pois)
+    assert all(b > a for a, b in zip(mu, mu[1:])), mu
+    for m, d in zip(mu[1:], demt[1:]):
+        assert abs(m / d - 1.0) < 0.10, (mu, demt)
+    for (p, _), r in zip(cases[1:], rho[1:]):  # the droplets neither dissolve nor grow
+        assert abs(float((r[0] > 0.5).mean()) / p - 1.0) < 0.1, (p, float((r[0] > 0.5).mean()))
