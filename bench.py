@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle steps (0: auto, ~15 s)")
     ap.add_argument("--chunk", type=int, default=0, help="strip height (0: autotune)")
-    ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 62)")
+    ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 58)")
     ap.add_argument("--balance", type=int, default=0, help="with --width: workgroups per CU")
     ap.add_argument("--batched-steps", type=int, default=1000, help="0 skips the batched form")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint form")
@@ -239,8 +239,8 @@ def main():
 
     # strip height: autotuned (untimed) unless given
     if a.chunk > 0 or a.balance > 0:
-        tune.apply(sim, a.width or 62, a.chunk, a.balance)
-        tuning = {"best": a.chunk, "width": a.width or 62, "balance": a.balance}
+        tune.apply(sim, a.width or 58, a.chunk, a.balance)
+        tuning = {"best": a.chunk, "width": a.width or 58, "balance": a.balance}
     else:
         tuning = tune.tune(sim, use_cache=False)
 

@@ -116,7 +116,10 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
              const double *rhoB0, void *workspace, uint64_t workspace_bytes, void *stream);
 
 /* Advance every instance by nsteps >= 0 time steps (Eq. 1).  Asynchronous on
- * the context's stream; long runs replay a captured HIP graph. */
+ * the context's stream; long runs replay a captured HIP graph.  The step
+ * moves only the populations: the calls that read densities (observables,
+ * fields, pressure tensor, recording) first compute those of the current
+ * state with one density pass, once per state. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
 /* Time steps taken since lbm_init (or the last lbm_set_populations). */
@@ -161,9 +164,8 @@ int lbm_set_populations(lbm_ctx *ctx, int32_t inst, const float *f_dev);
 
 /* Interaction plus body forces F_k (Eqs. 8, 9, F^b) of instance inst for the
  * given densities rho_dev[2][ny][nx] (device, FP32) into F_dev[2][2][ny][nx]
- * (component, axis).  Uses the step's own force code; overwrites the
- * instance's internal density buffer (the next lbm_step recomputes it).
- * Asynchronous. */
+ * (component, axis).  Uses the step's own force code and a scratch density
+ * buffer of the context (not the current state's).  Asynchronous. */
 int lbm_forces(lbm_ctx *ctx, int32_t inst, const float *rho_dev, float *F_dev);
 
 /* Device-to-device copy of nbytes through the library's own streaming copy
@@ -187,9 +189,9 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
 int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows);
 int32_t lbm_get_tiling(const lbm_ctx *ctx);
 
-/* Output columns per strip of the fused step, in [16, 510] (default 62).  A
- * strip is one workgroup of 1, 2, 4 or 8 wavefronts (up to 62, 126, 254 or
- * 510 columns).  A multiple of 16 places strips at multiples of cols, so
+/* Output columns per strip of the fused step, in [16, 506] (default 58).  A
+ * strip is one workgroup of 1, 2, 4 or 8 wavefronts (up to 58, 122, 250 or
+ * 506 columns).  A multiple of 16 places strips at multiples of cols, so
  * that every row of output starts on a 64-byte boundary; any other value
  * splits each row into ceil(nx / cols) strips of balanced width.  Results
  * are bitwise identical for every value.  Synchronises the stream and

@@ -64,7 +64,7 @@ struct StripPlan {
     std::vector<int> first;
 };
 
-// Column strips of an instance for output width W (<= 510; a strip of W
+// Column strips of an instance for output width W (<= 506; a strip of W
 // columns is one workgroup of strip_waves(W) wavefronts): ceil(nx / W)
 // strips, either of balanced width (W not a multiple of 16) or starting at
 // multiples of W (W a multiple of 16), so that every output row segment
@@ -84,6 +84,16 @@ std::vector<int2> column_strips(int nx, int W)
 }
 
 constexpr int NXCD = 8;  // XCDs of the chip; workgroup g is dealt to XCD g % 8
+
+// Every segment of a plan fits a strip of nw wavefronts: its lanes cover
+// the output columns, a collided halo column and HALO stencil columns on
+// each side (the fused step assumes this for its LDS ring).
+bool plan_fits(const StripPlan &P, int nw)
+{
+    for (const int4 &t : P.segs)
+        if ((t.w & 0xffff) > 64 * nw - 2 - 2 * HALO) return false;
+    return true;
+}
 
 // Uniform plan: rows split into ceil(ny / H) chunks of balanced height, one
 // segment per workgroup.  The segments are ordered so that consecutive
@@ -296,6 +306,9 @@ struct lbm_ctx {
     int width = DEFAULT_WIDTH;
     int balance = 0;   // workgroups per CU of a balanced plan (0: uniform chunks)
     int ncu = 256;     // compute units of the device
+    // rho[par] holds the densities of the state in f[par] (the plain step
+    // does not write them; ensure_rho computes them when a kernel reads them)
+    bool rho_ok[2] = {false, false};
     std::string err;
 };
 
@@ -399,6 +412,10 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
             ctx->ncu = ncu;
     }
     StripPlan plan = plan_uniform(params, n_inst, ctx->chunk, ctx->width);
+    if (!plan_fits(plan, strip_waves(ctx->width))) {
+        delete ctx;
+        return fail(nullptr, LBM_EINVAL, "strip wider than its workgroup");
+    }
     const std::vector<int4> &strips = plan.segs;
     d.nstrips = (int)strips.size();
     d.nwg = (int)plan.first.size() - 1;
@@ -449,7 +466,19 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     if ((e = launch_init(d, drho0p, st)) != hipSuccess) return bail(e, "init kernel");
     // the pageable host sources must stay valid until the copies complete
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "synchronise after init");
+    ctx->rho_ok[0] = true;  // the init kernels write the densities of f[0]
     *out = ctx;
+    return LBM_OK;
+}
+
+// Densities of the current state for the kernels that read rho[par]
+// (observables, fields, the pressure tensor, a recorded window's first slot).
+static int ensure_rho(lbm_ctx *ctx)
+{
+    if (ctx->rho_ok[ctx->par]) return LBM_OK;
+    hipError_t e = launch_density(ctx->dev, ctx->par, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "density kernel");
+    ctx->rho_ok[ctx->par] = true;
     return LBM_OK;
 }
 
@@ -503,6 +532,7 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps)
     }
     int rc = step_eager(ctx, r, st);
     if (rc != LBM_OK) return rc;
+    if (nsteps > 0) ctx->rho_ok[0] = ctx->rho_ok[1] = false;
     ctx->steps += nsteps;
     return LBM_OK;
 }
@@ -513,6 +543,8 @@ int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar)
 {
     CTX_CHECK(ctx);
     if (!out) return fail(ctx, LBM_EINVAL, "null output");
+    int rc = ensure_rho(ctx);
+    if (rc) return rc;
     hipStream_t st = ctx->stream;
     const double margin = 12.0;  // outer pressure shell starts 12 lattice units beyond R_eff
     hipError_t e = launch_observables(ctx->dev, ctx->par, margin, st);
@@ -575,6 +607,7 @@ int lbm_fields(lbm_ctx *ctx, int32_t inst, float *rho_dev, float *u_dev)
 {
     CTX_CHECK(ctx);
     int rc = check_inst(ctx, inst);
+    if (!rc) rc = ensure_rho(ctx);
     if (rc) return rc;
     hipError_t e = launch_fields(ctx->dev, ctx->par, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "fields kernels");
@@ -602,6 +635,7 @@ int lbm_set_populations(lbm_ctx *ctx, int32_t inst, const float *f_dev)
     if (!f_dev) return fail(ctx, LBM_EINVAL, "null input");
     hipError_t e = launch_import(ctx->dev, inst, ctx->par, f_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "import kernel");
+    ctx->rho_ok[ctx->par] = true;  // the import recomputes the densities of every instance
     ctx->steps = 0;
     return LBM_OK;
 }
@@ -612,6 +646,7 @@ int lbm_forces(lbm_ctx *ctx, int32_t inst, const float *rho_dev, float *F_dev)
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
     if (!rho_dev || !F_dev) return fail(ctx, LBM_EINVAL, "null argument");
+    ctx->rho_ok[ctx->par ^ 1] = false;  // the caller's densities go to rho[par ^ 1]
     hipError_t e = launch_forces(ctx->dev, inst, ctx->par, rho_dev, F_dev, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "force kernels");
     return LBM_OK;
@@ -639,7 +674,7 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
     int rc = LBM_OK;
-    // the density pass first, so that the step kernel reads current densities
+    ctx->rho_ok[ctx->par ^ 1] = false;  // the launches overwrite f[par ^ 1]
     for (int j = 0; j < N_STEP_KERNELS && j < max_k && rc == LBM_OK; ++j) {
         hipError_t e = launch_step_kernel(ctx->dev, j, ctx->par, st);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -667,6 +702,7 @@ static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance)
                          : plan_uniform(ctx->params.data(), ctx->n_inst, rows, cols);
     if ((int)plan.segs.size() > ctx->layout.max_strips)
         return fail(ctx, LBM_EINVAL, "strip table overflow");
+    if (!plan_fits(plan, strip_waves(cols))) return fail(ctx, LBM_EINVAL, "strip wider than its workgroup");
     // the tables are read by kernels already queued: order the copies after them
     HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, plan.segs.data(), sizeof(int4) * plan.segs.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
@@ -699,7 +735,7 @@ int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
 {
     CTX_CHECK(ctx);
     if (cols < MIN_WIDTH || cols > MAX_STRIP_COLS)
-        return fail(ctx, LBM_EINVAL, "cols must be in [16, 510]");
+        return fail(ctx, LBM_EINVAL, "cols must be in [16, 506]");
     return set_strips(ctx, ctx->chunk, cols, ctx->balance);
 }
 
@@ -777,6 +813,7 @@ static bool overlaps(const void *a, uint64_t na, const void *b, uint64_t nb)
 // (free between steps: the next step overwrites it).
 static const float *packed_state(lbm_ctx *ctx, int inst, const float *f_dev, hipError_t *e)
 {
+    ctx->rho_ok[ctx->par ^ 1] = false;
     *e = launch_import(ctx->dev, inst, ctx->par ^ 1, f_dev, ctx->stream);
     return ctx->hinst[inst].f[ctx->par ^ 1];
 }
@@ -808,6 +845,8 @@ int lbm_pressure(lbm_ctx *ctx, int32_t inst, float *P_dev, double *line_tension)
     int rc = check_inst(ctx, inst);
     if (rc) return rc;
     if (!P_dev) return fail(ctx, LBM_EINVAL, "null output");
+    rc = ensure_rho(ctx);
+    if (rc) return rc;
     const lbm_params &p = ctx->params[inst];
     const KInst &K = ctx->hinst[inst];
     // block partials and the final sum in the instance's field scratch
@@ -841,9 +880,12 @@ int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
     const InstLayout &L = ctx->layout.inst[inst];
     const KInst &K = ctx->hinst[inst];
     const int64_t S = L.fsize + L.rsize;
+    rc = ensure_rho(ctx);
+    if (rc) return rc;
     hipStream_t st = ctx->stream;
     // slot 0 = the current state; step j reads slot j and writes slot j + 1
-    // (the last step the context's own buffers, so the context advances)
+    // (the last step the context's own buffers, so the context advances);
+    // these launches write the densities of every instance
     HIP_TRY(ctx, hipMemcpyAsync(f_store_dev, K.f[ctx->par], L.fsize * sizeof(float),
                                 hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipMemcpyAsync(f_store_dev + L.fsize, K.rho[ctx->par], L.rsize * sizeof(float),
@@ -851,11 +893,13 @@ int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev)
     for (int64_t j = 0; j < nsteps; ++j) {
         float *cur = f_store_dev + j * S, *nxt = f_store_dev + (j + 1) * S;
         const bool last = j + 1 == nsteps;
-        const StepOvr o{inst, cur, cur + L.fsize, last ? K.f[ctx->par ^ 1] : nxt,
-                        last ? K.rho[ctx->par ^ 1] : nxt + L.fsize};
+        const StepOvr o{inst, cur, last ? K.f[ctx->par ^ 1] : nxt,
+                        last ? K.rho[ctx->par ^ 1] : nxt + L.fsize, 1};
         hipError_t e = launch_step_ovr(ctx->dev, ctx->par, o, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
         ctx->par ^= 1;
+        ctx->rho_ok[ctx->par] = true;
+        ctx->rho_ok[ctx->par ^ 1] = false;
     }
     ctx->steps += nsteps;
     return LBM_OK;

@@ -41,11 +41,11 @@ constexpr int TY = 4;    // auxiliary 2-D tiles: height (4 wavefronts per block)
 constexpr int NTHREADS = TX * TY;
 constexpr int HALO = 2;  // radius of the D2Q25 stencil
 
-// fused step: one wavefront per strip; lane l collides column X0 - 1 + l
-constexpr int SW = 64;           // lanes = collided columns of a strip
-constexpr int SWO = SW - 2;      // output columns of a full strip
-constexpr int RW = SW + 2 * HALO;  // density-ring columns (collided columns + stencil halo)
-constexpr int RR = 2 * HALO + 1;   // density-ring rows
+// fused step: the lanes of a strip load its output columns, one collided
+// halo column and HALO stencil columns on each side
+constexpr int SW = 64;                  // lanes of a one-wavefront strip
+constexpr int SWO = SW - 2 - 2 * HALO;  // output columns of a full one-wavefront strip
+constexpr int RR = 2 * HALO + 1;        // density-ring rows
 
 // number of FP32 planes in the per-instance field scratch
 constexpr int NFLD = 9;
@@ -247,24 +247,6 @@ __device__ __forceinline__ void tile_force(const KInst &P, const Tile &T, int cx
 {
     stencil_force(P, TileAcc{T, cx, cy}, F);
 }
-
-// Density ring of the fused step: RR rows (a rolling window over lattice
-// rows) of RW columns, column j holding lattice column X0 - 1 - HALO + j.
-struct Ring {
-    float rho[2][RR][RW];
-    float psi[2][RR][RW];
-    float dev[2][RR][RW];  // density deviations (own-node term of the collision)
-};
-
-// accessor into the ring: slot[dy + 2] is the ring row of lattice row c + dy,
-// cx the ring column of the node
-struct RingAcc {
-    const Ring &R;
-    const int *slot;
-    int cx;
-    __device__ float psi(int k, int dx, int dy) const { return R.psi[k][slot[dy + HALO]][cx + dx]; }
-    __device__ float rho(int k, int dx, int dy) const { return R.rho[k][slot[dy + HALO]][cx + dx]; }
-};
 
 // Momentum sum_i f_i e_i of one component as antisymmetric differences.
 __device__ __forceinline__ void mom9(const float f[9], float &mx, float &my)

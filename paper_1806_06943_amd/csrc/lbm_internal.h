@@ -32,17 +32,20 @@ struct Dev {
 };
 
 // wavefronts per strip for a strip of `cols` output columns
-constexpr int strip_waves(int cols) { return cols <= 62 ? 1 : cols <= 126 ? 2 : cols <= 254 ? 4 : 8; }
-constexpr int MAX_STRIP_COLS = 8 * 64 - 2;
+constexpr int strip_waves(int cols) { return cols <= 58 ? 1 : cols <= 122 ? 2 : cols <= 250 ? 4 : 8; }
+constexpr int MAX_STRIP_COLS = 8 * 64 - 6;
 
 hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
 hipError_t launch_step(const Dev &d, int par, hipStream_t st);
-// Buffers that replace one instance's ping-pong pair for one launch of the
-// fused step (a window recorded in place); inst < 0: none.
+// Options of one launch of the fused step: buffers that replace one
+// instance's ping-pong pair (a window recorded in place; inst < 0: none),
+// and whether the launch writes rho(t + 1) of every instance (wrho 1) or of
+// none (0: the step itself never reads it).
 struct StepOvr {
     int inst;
-    const float *fin, *rin;
+    const float *fin;
     float *fout, *rout;
+    int wrho;
 };
 hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t st);
 hipError_t launch_density(const Dev &d, int par, hipStream_t st);

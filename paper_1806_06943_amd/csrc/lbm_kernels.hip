@@ -117,8 +117,8 @@ __device__ __forceinline__ float from_right(float v)
 }
 
 // Density ring of a strip of NW wavefronts: RR rows (a rolling window over
-// lattice rows) of 64 NW + 4 columns, column j holding lattice column
-// X0 - 1 - HALO + j.
+// lattice rows) of 64 NW columns (plus 4 that no stencil of a used lane
+// reads), column j holding lattice column X0 - 1 - HALO + j.
 template <int NW>
 struct RingW {
     static constexpr int W = 64 * NW + 2 * HALO;
@@ -139,45 +139,47 @@ struct RingAccW {
 };
 
 // One workgroup of NW wavefronts advances its segments, one after the
-// other, by one time step; a segment is a strip of wo <= 64 NW - 2 output
+// other, by one time step; a segment is a strip of wo <= 64 NW - 6 output
 // columns [X0, X0 + wo) and ho output rows [Y0, Y0 + ho).
-// Thread L owns lattice column X0 - 1 + L; threads 0 and wo + 1 are the
-// one-column halo whose collision the neighbouring strips also compute.  The
-// workgroup marches down the rows:
-//   * an LDS ring holds rho and psi of rows c-2 .. c+2 (columns X0-3 ..
-//     X0+64NW) for the force stencil of collided row c;
+// Thread L owns lattice column X0 - 3 + L: threads 0 .. wo + 5 load their
+// column, threads 2 .. wo + 3 collide it (threads 2 and wo + 3 are the
+// one-column halo whose collision the neighbouring strips also compute).
+// The workgroup marches down the rows:
+//   * the populations of each row are read once, three rows ahead of their
+//     collision: their sums give rho and psi of that row in an LDS ring that
+//     holds rows c-2 .. c+2 for the force stencil of collided row c, and the
+//     populations of rows c .. c+2 wait in registers;
 //   * collided rows c-2 (upward populations) and c-1 (all) stay in registers;
 //   * output row o = c - 1 pulls f_i(x, o) = f*_i(x - e_i) from rows o-1, o,
 //     o+1: the x shift by one column is a DPP lane shift inside a wavefront
 //     and, across the boundary between two wavefronts, an exchange of the
 //     six edge values per component through LDS; bounce-back takes the
 //     node's own reflected population next to a wall;
-//   * f(t+1) and rho(t+1) of the output row are written.
+//   * f(t+1) of the output row is written, and rho(t+1) when the launch
+//     asks for it (for the other kernels and the caller: the step itself
+//     never reads it).
 // The loop body has no lane-divergent branches on global memory: every lane
 // loads a valid column or, where nothing it loads is used (idle lanes beyond
 // the halo), zeros, rows beyond a wall read a clamped row whose values are
 // not used, and lanes that must not write give an offset beyond the buffer,
 // which the descriptor's range check drops
 // (buffers stay below 2 GiB, so that offset plus any segment offset cannot
-// wrap into range).  Memory waits are then exact.  The next row's
-// populations are loaded while the current row is collided.  Two barriers
-// per row: after the collision (the ring row of c - 2 and the edge values
-// are then free / published) and after the ring update.
+// wrap into range).  Memory waits are then exact.  The loads of row c + 3
+// are in flight while row c is collided.  Two barriers per row: after the
+// collision (the ring row of c - 2 and the edge values are then free /
+// published) and after the ring update.
 // FS selects the forcing: 0 the Guo term with the common velocity (Eq. 5),
 // 1 the velocity shift of the original model (momenta without F/2, BGK
 // towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
-// Reads f[par], rho[par]; writes f[par ^ 1], rho[par ^ 1].
-// Register budget: three waves per SIMD (168 VGPRs) for strips of two or
-// more wavefronts, which the fastest plans keep at two waves per SIMD or
-// fewer anyway (eight-wave strips: one workgroup per CU); at four (128
-// VGPRs) the step spills, and the spill reload's wait drains the row's
-// outstanding stores.  One-wave strips fit in 128.
+// Reads f[par]; writes f[par ^ 1] and, with ovr.wrho, rho[par ^ 1].
+// Register budget: three waves per SIMD (168 VGPRs), which every strip
+// width meets without spilling although four rows of populations are live
+// across the collision.
 template <int NW, int FS>
-__global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
+__global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
     const KInst *__restrict__ insts, const int4 *__restrict__ segs, const int *__restrict__ first,
     int par, StepOvr ovr)
 {
-    constexpr int NL = 64 * NW;
     __shared__ RingW<NW> R;
     // edge values of each wavefront for its neighbours: [wave][side][6]
     __shared__ float edge[NW][2][6];
@@ -201,33 +203,22 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
     const bool ov = t.x == ovr.inst;
     const __amdgpu_buffer_rsrc_t fin = make_rsrc(ov ? ovr.fin : G.f[par], (uint32_t)ny * frowb);
     const __amdgpu_buffer_rsrc_t fout = make_rsrc(ov ? ovr.fout : G.f[par ^ 1], (uint32_t)ny * frowb);
-    const __amdgpu_buffer_rsrc_t rin = make_rsrc(ov ? ovr.rin : G.rho[par], (uint32_t)ny * rrowb);
     const __amdgpu_buffer_rsrc_t rout = make_rsrc(ov ? ovr.rout : G.rho[par ^ 1], (uint32_t)ny * rrowb);
-    const uint32_t xc = (uint32_t)wrapi(X0 - 1 + L, nx);  // collided column
-    const bool outl = (L >= 1) && (L <= wo);
     // out-of-range offset: a load returns 0 without a memory request, a store
     // is dropped (offsets below 2 GiB plus this one cannot wrap into range)
     constexpr uint32_t DROP = 0x80000000u;
-    // lanes beyond the right halo column (L > wo + 1) collide values that no
-    // output uses: their population loads read zeros instead of memory
-    const bool needf = L <= wo + 1;
-    const uint32_t xf16 = needf ? xc * 16u : DROP, xf8 = needf ? xc * 8u : DROP;
-    // ring column j holds lattice column X0 - 1 - HALO + j; thread L fills
-    // j = L (both components) and one (extra column, component) pair: lanes
-    // with the same pair load the same value and write it to the same place.
-    // The stencils of lanes 0 .. wo + 1 read columns up to wo + 1 + 2 HALO;
-    // columns beyond are filled from zeros.
+    // Thread L owns lattice column X0 - 1 - HALO + L.  Lanes 0 .. wo + 1 +
+    // 2 HALO load that column's populations: their densities fill ring
+    // column L, and the populations wait in registers for the node's own
+    // collision three rows later.  Lanes HALO .. wo + 1 + HALO collide (the
+    // outer two are the one-column halo whose collision the neighbouring
+    // strips also compute), lanes HALO + 1 .. wo + HALO write.  Lanes beyond
+    // read zeros and write nothing.
     const int jmax = wo + 1 + 2 * HALO;
-    const uint32_t gx0b = L <= jmax ? (uint32_t)wrapi(X0 - 1 - HALO + L, nx) * 8u : DROP;
-    const int xe = l & 3, ke = (l >> 2) & 1;
-    const uint32_t gxeb = NL + xe <= jmax
-                              ? (uint32_t)wrapi(X0 - 1 - HALO + NL + xe, nx) * 8u + (uint32_t)ke * 4u
-                              : DROP;
-    // per-lane parameters of the extra column's component, selected once (a
-    // lane-dependent index into the parameter copy would put it in scratch)
-    const float ref_e = ke ? P.rho_ref[1] : P.rho_ref[0];
-    const float rwall_e = ke ? P.rho_wall[1] : P.rho_wall[0];
-    const float pwall_e = ke ? P.psi_wall[1] : P.psi_wall[0];
+    const bool outl = (L >= HALO + 1) && (L <= wo + HALO);
+    const uint32_t xl = (uint32_t)wrapi(X0 - 1 - HALO + L, nx);
+    const bool needf = L <= jmax;
+    const uint32_t xf16 = needf ? xl * 16u : DROP, xf8 = needf ? xl * 8u : DROP;
 
     // lattice row r -> wrapped row index, or -1 beyond a wall (general
     // form, used once per cursor); cursors then advance by one row
@@ -245,39 +236,10 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
         else
             q.i = (q.i + 1 == ny) ? 0 : q.i + 1;
     };
-    struct RingVals {
-        float a, b, e;  // density deviations of A, B at column L; extra-column value
-    };
-    // rows beyond a wall read row 0 (valid memory); ring_store replaces the
-    // values.  A row that no later collision needs (live false: the loads of
-    // the last iteration) reads zeros instead of memory.
-    auto ring_load = [&](int ri, bool live) {
-        const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * rrowb;
-        const u32x2 ab = bload2(rin, live ? ro + gx0b : DROP, 0);
-        RingVals v;
-        v.a = __uint_as_float(ab.x);
-        v.b = __uint_as_float(ab.y);
-        v.e = bload(rin, live ? ro + gxeb : DROP, 0);
-        return v;
-    };
-    auto ring_store = [&](int slot, int ri, const RingVals &v) {
-        const bool wall = ri < 0;
-        const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + v.a;
-        const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + v.b;
-        R.rho[0][slot][L] = ra;
-        R.rho[1][slot][L] = rb;
-        R.psi[0][slot][L] = wall ? P.psi_wall[0] : psi_of(P, ra);
-        R.psi[1][slot][L] = wall ? P.psi_wall[1] : psi_of(P, rb);
-        R.dev[0][slot][L] = v.a;
-        R.dev[1][slot][L] = v.b;
-        if (NL <= jmax) {  // uniform: the strip's stencils reach the extra columns
-            const float re = wall ? rwall_e : ref_e + v.e;
-            R.dev[ke][slot][NL + xe] = v.e;
-            R.rho[ke][slot][NL + xe] = re;
-            R.psi[ke][slot][NL + xe] = wall ? pwall_e : psi_of(P, re);
-        }
-    };
-    // four float4 planes and one float2 plane per row (q = 9 k + i in order)
+    // four float4 planes and one float2 plane per row (q = 9 k + i in order);
+    // rows beyond a wall read row 0 (valid memory, never used), and a row
+    // that nothing needs (live false: the loads of the last iteration)
+    // reads zeros instead of memory
     auto load_f = [&](int ri, bool live, float f[2][9]) {
         const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * frowb;
         const uint32_t o16 = live ? ro + xf16 : DROP, o8 = live ? ro + xf8 : DROP;
@@ -298,22 +260,52 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[k][i] = q[9 * k + i];
     };
+    // ring column L of a row from that row's populations at column L: the
+    // density deviations are the same correctly rounded sums that the step
+    // writes as rho(t + 1) (Eq. 6); a row beyond a wall takes the wall's
+    // densities instead
+    auto ring_store = [&](int slot, int ri, const float q[2][9]) {
+        const bool wall = ri < 0;
+        const float da = sum9(q[0]), db = sum9(q[1]);
+        const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
+        const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + db;
+        R.rho[0][slot][L] = ra;
+        R.rho[1][slot][L] = rb;
+        R.psi[0][slot][L] = wall ? P.psi_wall[0] : psi_of(P, ra);
+        R.psi[1][slot][L] = wall ? P.psi_wall[1] : psi_of(P, rb);
+        R.dev[0][slot][L] = da;
+        R.dev[1][slot][L] = db;
+    };
 
-    // ring rows Y0 - 3 .. Y0 + 1 into slots 0..4; slot[d] is the slot of row
-    // c - 2 + d for the row c being collided
+    // ring rows Y0 - 3 .. Y0 + 1 into slots 0..4 (slot[d] is the slot of row
+    // c - 2 + d for the row c being collided); the populations of rows
+    // Y0 - 1, Y0 and Y0 + 1 stay in fa, fb, fc for their collisions
     int slot[RR];
     Cursor cr = cursor(Y0 - 1 - HALO);  // next row to enter the ring
-    for (int q = 0; q < RR; ++q) {
-        ring_store(q, cr.i, ring_load(cr.i, true));
-        slot[q] = q;
-        advance(cr);
+    float fa[2][9], fb[2][9], fc[2][9];
+    {
+        float t0[2][9], t1[2][9];
+        int ri[RR];
+#pragma unroll
+        for (int q = 0; q < RR; ++q) {
+            ri[q] = cr.i;
+            slot[q] = q;
+            advance(cr);
+        }
+        load_f(ri[0], true, t0);
+        load_f(ri[1], true, t1);
+        load_f(ri[2], true, fa);
+        load_f(ri[3], true, fb);
+        load_f(ri[4], true, fc);
+        ring_store(0, ri[0], t0);
+        ring_store(1, ri[1], t1);
+        ring_store(2, ri[2], fa);
+        ring_store(3, ri[3], fb);
+        ring_store(4, ri[4], fc);
     }
     __syncthreads();
 
     Cursor cc = cursor(Y0 - 1);  // row being collided
-    Cursor cf = cc;              // row of the prefetched populations
-    float fn[2][9];
-    load_f(cf.i, true, fn);
     float Sprev[2][9], Uprev[2][3];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -324,32 +316,27 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
 
     const int nit = ho + 2;
     for (int it = 0; it < nit; ++it) {
-        // the next density row first, then the next population row (the last
+        // the populations of row c + 3, for the ring after this collision
+        // and for their own collision three iterations on (the last
         // iteration needs neither: its loads read zeros)
         const bool more = it + 1 < nit;
         const int rnext = cr.i;
-        const RingVals vnext = ring_load(rnext, more);
-        float f[2][9];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f[k][i] = fn[k][i];
-        advance(cf);
-        load_f(cf.i, more, fn);
+        float fn[2][9];
+        load_f(rnext, more, fn);
 
         // collide row c (a row beyond a wall is collided from clamped data
         // and never used)
         float S[2][9];
         {
             float F[2][2];
-            stencil_force(P, RingAccW<RingW<NW>>{R, slot, L + HALO}, F);
+            stencil_force(P, RingAccW<RingW<NW>>{R, slot, L}, F);
             float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                drho[k] = R.dev[k][slot[HALO]][L + HALO];
-                rho[k] = R.rho[k][slot[HALO]][L + HALO];
+                drho[k] = R.dev[k][slot[HALO]][L];
+                rho[k] = R.rho[k][slot[HALO]][L];
                 float mx, my;
-                mom9(f[k], mx, my);
+                mom9(fa[k], mx, my);
                 jx[k] = FS ? mx : fmaf(0.5f, F[k][0], mx);
                 jy[k] = FS ? my : fmaf(0.5f, F[k][1], my);
             }
@@ -360,10 +347,10 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
                 if constexpr (FS) {
                     // equilibrium velocity shifted by tau_k F_k / rho_k
                     const float s = recip(rho[k] * P.it[k]);
-                    collide(P, k, f[k], drho[k], rho[k], 0.0f, 0.0f, fmaf(F[k][0], s, ux),
+                    collide(P, k, fa[k], drho[k], rho[k], 0.0f, 0.0f, fmaf(F[k][0], s, ux),
                             fmaf(F[k][1], s, uy), S[k]);
                 } else {
-                    collide(P, k, f[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
+                    collide(P, k, fa[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
                 }
             }
         }
@@ -404,10 +391,10 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
             const bool wlo = walls && o == 0;
             const bool whi = walls && o == ny - 1;
             const bool st = outl && it >= 2;
-            const uint32_t xo = (uint32_t)(X0 - 1 + L);
+            const uint32_t xo = (uint32_t)(X0 - 1 - HALO + L);
             const uint32_t off4 = st ? (uint32_t)o * frowb + xo * 16u : DROP;
             const uint32_t off2 = st ? (uint32_t)o * frowb + xo * 8u : DROP;
-            const uint32_t roff = st ? (uint32_t)o * rrowb + xo * 8u : DROP;
+            const uint32_t roff = st && ovr.wrho ? (uint32_t)o * rrowb + xo * 8u : DROP;
             // component A fills planes 0, 1 and the first lane of plane 2;
             // component B the rest of plane 2, plane 3 and the float2 plane
             float a8 = 0.0f, ra = 0.0f;
@@ -461,10 +448,18 @@ __global__ __launch_bounds__(64 * NW, NW >= 2 ? 3 : 4) void k_fused_step(
 #pragma unroll
             for (int d = 0; d < RR - 1; ++d) slot[d] = slot[d + 1];
             slot[RR - 1] = freed;
-            ring_store(freed, rnext, vnext);
+            ring_store(freed, rnext, fn);
             __syncthreads();  // the new ring row and the consumed edges before reuse
             advance(cr);
         }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                fa[k][i] = fb[k][i];
+                fb[k][i] = fc[k][i];
+                fc[k][i] = fn[k][i];
+            }
         advance(cc);
     }
     }  // segments
@@ -978,7 +973,7 @@ hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t 
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)
 {
-    return launch_step_ovr(d, par, StepOvr{-1, nullptr, nullptr, nullptr, nullptr}, st);
+    return launch_step_ovr(d, par, StepOvr{-1, nullptr, nullptr, nullptr, 0}, st);
 }
 
 const char *step_kernel_name(int j)

@@ -26,14 +26,14 @@ CANDIDATES = (2, 3, 4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
 MIN_HEIGHT = 2  # the smallest strip height lbm_set_tiling accepts
 # (output columns per strip): one wavefront per strip, balanced / aligned,
 # then strips of 2, 4 and 8 wavefronts, balanced / aligned
-WIDTHS = (62, 48, 126, 112, 254, 240, 510, 496)
+WIDTHS = (58, 48, 122, 112, 250, 240, 506, 496)
 CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
                                                         "lbm_tiling.json"))
 
 
 def _key(sim, arch: str) -> str:
     shapes = sorted({(p.nx, p.ny) for p in sim.params})
-    return f"v2|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
+    return f"v3|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
         (f"|+{len(shapes) - 8}" if len(shapes) > 8 else "")
 
 
@@ -136,7 +136,7 @@ def _main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--workload", default="spinodal",
                     choices=("spinodal", "emulsion", "batched", "adjoint_array"))
-    ap.add_argument("--widths", default="240,496,126,62,48")
+    ap.add_argument("--widths", default="240,496,122,58,48")
     ap.add_argument("--heights", default="8:72:2", help="start:stop:step")
     ap.add_argument("--balances", default="1,2,3,4")
     ap.add_argument("--nrep", type=int, default=30)

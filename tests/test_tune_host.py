@@ -55,5 +55,5 @@ def test_no_height_below_the_library_minimum_is_tried(monkeypatch):
     # one-wave strips on a wide lattice: k * ncu workgroups need heights below 4
     sim = FakeSim(2048, 2048)
     applied = install(monkeypatch, sim, 34)
-    hs = tune.fitted_heights(sim, 62, 256)
+    hs = tune.fitted_heights(sim, 58, 256)
     assert min(applied) >= tune.MIN_HEIGHT and all(h >= tune.MIN_HEIGHT for h in hs)
