@@ -34,23 +34,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (2-comp) + % HBM peak; fwd+adjoint MLUPS vs plain fwd at stated error"
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, public figure
-# k_fused_step per lattice update: read + write 18 FP32 populations (144 B),
-# read + write 2 FP32 densities (16 B)
+# Stated algorithmic bytes per lattice update of the fused single-pass step:
+# read + write 18 FP32 populations (144 B), read + write 2 FP32 densities
+# (16 B).  The roofline fraction is priced at this figure.
 B_PER_LU = 160.0
+# What k_fused_step itself must move: it derives the densities from the
+# populations it loads and writes none, so only the populations (144 B).
+KERNEL_B_PER_LU = 144.0
 DOMINANT = "k_fused_step"
 
 # HBM bytes per k_fused_step launch on this workload from rocprofv3 --pmc
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
 # library), per strip plan (width, height, workgroups per CU), valid only for
 # the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "42b8ed9e1d32e6e1",
-                    "plans": {(240, 37, 0): (177298.7 * 2.0 * 1024, 327689.7 * 1024),
-                              (240, 38, 0): (177433.1 * 2.0 * 1024, 327687.5 * 1024),
-                              (240, 40, 0): (177410.9 * 2.0 * 1024, 327687.0 * 1024),
-                              (240, 42, 0): (177222.0 * 2.0 * 1024, 327683.3 * 1024),
-                              (510, 42, 0): (173981.5 * 2.0 * 1024, 328308.0 * 1024),
-                              (126, 46, 0): (174727.0 * 2.0 * 1024, 331175.4 * 1024),
-                              (254, 40, 0): (175528.7 * 2.0 * 1024, 329300.1 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "505d73267c251b42",
+                    "plans": {(506, 42, 0): (169361.0 * 2.0 * 1024, 295175.9 * 1024),
+                              (496, 42, 0): (170583.8 * 2.0 * 1024, 294912.2 * 1024),
+                              (240, 37, 0): (173214.6 * 2.0 * 1024, 294914.3 * 1024),
+                              (240, 38, 0): (172711.5 * 2.0 * 1024, 294914.0 * 1024),
+                              (240, 40, 0): (172181.4 * 2.0 * 1024, 294913.4 * 1024),
+                              (250, 40, 0): (171654.7 * 2.0 * 1024, 295970.4 * 1024),
+                              (122, 46, 0): (168268.3 * 2.0 * 1024, 296444.4 * 1024),
+                              (112, 52, 0): (165999.2 * 2.0 * 1024, 294912.2 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
@@ -322,6 +327,8 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE)",
                      "algorithmic_bytes": B_PER_LU * N,
                      "kernel": DOMINANT, "bytes_per_lu": B_PER_LU,
+                     "kernel_bytes_per_lu": KERNEL_B_PER_LU,
+                     "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / B_PER_LU, 1),
                      "kernel_ms": round(k_ms, 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
         "alg_gbps_whole_step": round(mlups * 1e6 * B_PER_LU / 1e9, 1),

@@ -176,7 +176,7 @@ struct RingAccW {
 // width meets without spilling although four rows of populations are live
 // across the collision.
 template <int NW, int FS>
-__global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
+__global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     const KInst *__restrict__ insts, const int4 *__restrict__ segs, const int *__restrict__ first,
     int par, StepOvr ovr)
 {
@@ -306,27 +306,30 @@ __global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
     __syncthreads();
 
     Cursor cc = cursor(Y0 - 1);  // row being collided
-    float Sprev[2][9], Uprev[2][3];
+    // collided values of two consecutive rows (S of row c, Sprev of row
+    // c - 1) and the upward populations of row c - 2
+    float Sa[2][9], Sb[2][9], Uprev[2][3], fd[2][9];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Sprev[k][i] = 0.0f;
+        for (int i = 0; i < 9; ++i) Sb[k][i] = 0.0f;
         Uprev[k][0] = Uprev[k][1] = Uprev[k][2] = 0.0f;
     }
 
-    const int nit = ho + 2;
-    for (int it = 0; it < nit; ++it) {
+    // One row: collide row c from fa, load row c + 3 into fn.  The four
+    // population buffers and the two collided rows change roles from row to
+    // row by renaming (the loop below is unrolled by four), not by copies.
+    auto row = [&](int it, const int nit, float (&fa)[2][9], float (&fn)[2][9], float (&S)[2][9],
+                   const float (&Sprev)[2][9]) {
         // the populations of row c + 3, for the ring after this collision
-        // and for their own collision three iterations on (the last
-        // iteration needs neither: its loads read zeros)
+        // and for their own collision three rows on (the last row needs
+        // neither: its loads read zeros)
         const bool more = it + 1 < nit;
         const int rnext = cr.i;
-        float fn[2][9];
         load_f(rnext, more, fn);
 
         // collide row c (a row beyond a wall is collided from clamped data
         // and never used)
-        float S[2][9];
         {
             float F[2][2];
             stencil_force(P, RingAccW<RingW<NW>>{R, slot, L}, F);
@@ -424,12 +427,12 @@ __global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
                     bstore4(g[0], g[1], g[2], g[3], fout, off4, 0u);
                     bstore4(g[4], g[5], g[6], g[7], fout, off4, 16u * pb);
                     a8 = g[8];
-                    ra = sum9(g);
+                    if (ovr.wrho) ra = sum9(g);  // uniform: no sums when no densities are written
                 } else {
                     bstore4(a8, g[0], g[1], g[2], fout, off4, 32u * pb);
                     bstore4(g[3], g[4], g[5], g[6], fout, off4, 48u * pb);
                     bstore2(g[7], g[8], fout, off2, 64u * pb);
-                    bstore2(ra, sum9(g), rout, roff, 0u);
+                    if (ovr.wrho) bstore2(ra, sum9(g), rout, roff, 0u);
                 }
             }
         }
@@ -438,8 +441,6 @@ __global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
             Uprev[k][0] = Sprev[k][2];
             Uprev[k][1] = Sprev[k][5];
             Uprev[k][2] = Sprev[k][6];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Sprev[k][i] = S[k][i];
         }
         {
             // the slot of row c - 2 takes row c + 3 (after the last row too,
@@ -452,15 +453,14 @@ __global__ __launch_bounds__(64 * NW, 3) void k_fused_step(
             __syncthreads();  // the new ring row and the consumed edges before reuse
             advance(cr);
         }
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                fa[k][i] = fb[k][i];
-                fb[k][i] = fc[k][i];
-                fc[k][i] = fn[k][i];
-            }
         advance(cc);
+    };
+    const int nit = ho + 2;
+    for (int it = 0; it < nit; it += 4) {
+        row(it, nit, fa, fd, Sa, Sb);
+        if (it + 1 < nit) row(it + 1, nit, fb, fa, Sb, Sa);
+        if (it + 2 < nit) row(it + 2, nit, fc, fb, Sa, Sb);
+        if (it + 3 < nit) row(it + 3, nit, fd, fc, Sb, Sa);
     }
     }  // segments
 }
