@@ -47,15 +47,20 @@ DOMINANT = "k_fused_step"
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
 # library), per strip plan (width, height, workgroups per CU), valid only for
 # the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "505d73267c251b42",
-                    "plans": {(506, 42, 0): (169361.0 * 2.0 * 1024, 295175.9 * 1024),
-                              (496, 42, 0): (170583.8 * 2.0 * 1024, 294912.2 * 1024),
-                              (240, 37, 0): (173214.6 * 2.0 * 1024, 294914.3 * 1024),
-                              (240, 38, 0): (172711.5 * 2.0 * 1024, 294914.0 * 1024),
-                              (240, 40, 0): (172181.4 * 2.0 * 1024, 294913.4 * 1024),
-                              (250, 40, 0): (171654.7 * 2.0 * 1024, 295970.4 * 1024),
-                              (122, 46, 0): (168268.3 * 2.0 * 1024, 296444.4 * 1024),
-                              (112, 52, 0): (165999.2 * 2.0 * 1024, 294912.2 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "e86abe41d0bed219",
+                    "plans": {(58, 74, 0): (160251.8 * 2.0 * 1024, 295557.5 * 1024),
+                              (58, 64, 0): (163035.2 * 2.0 * 1024, 297303.5 * 1024),
+                              (48, 90, 0): (159362.1 * 2.0 * 1024, 294912.0 * 1024),
+                              (112, 52, 0): (167344.0 * 2.0 * 1024, 294913.7 * 1024),
+                              (122, 46, 0): (168568.3 * 2.0 * 1024, 296892.4 * 1024),
+                              (240, 37, 0): (174749.8 * 2.0 * 1024, 294921.4 * 1024),
+                              (240, 38, 0): (174132.0 * 2.0 * 1024, 294920.5 * 1024),
+                              (240, 40, 0): (173506.6 * 2.0 * 1024, 294920.4 * 1024),
+                              (250, 40, 0): (171892.1 * 2.0 * 1024, 296156.8 * 1024),
+                              (496, 42, 0): (170660.6 * 2.0 * 1024, 294912.3 * 1024),
+                              (506, 42, 0): (169468.1 * 2.0 * 1024, 295321.2 * 1024),
+                              (58, 40, 0): (173903.9 * 2.0 * 1024, 300025.7 * 1024),
+                              (58, 37, 0): (175822.0 * 2.0 * 1024, 300491.2 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 

@@ -64,7 +64,10 @@ def _ncu(sim) -> int:
         return 256
 
 
-def fitted_heights(sim, width: int, ncu: int, kmax: int = 4) -> list:
+FIT_KMAX = 8  # workgroups per CU up to which fitted heights are tried
+
+
+def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX) -> list:
     """For k = 1..kmax the smallest uniform strip height at which the launch has at
     most k * ncu workgroups (the count falls as the height grows)."""
     hmin = MIN_HEIGHT

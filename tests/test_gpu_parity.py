@@ -331,7 +331,7 @@ def test_small_and_ragged_lattices(torch, nx, ny, walls):
     assert np.abs(got - fo).max() < 1e-6
 
 
-@pytest.mark.parametrize("width", [506, 240, 122])
+@pytest.mark.parametrize("width", [506, 240, 122, 58])
 def test_fitted_heights_sit_just_under_cu_multiples(torch, width):
     """The tuner's fitted heights: at h the launch has at most k CUs' worth of
     workgroups, at h - 1 more (2048 x 2048 lattice; host planning only)."""
@@ -345,7 +345,7 @@ def test_fitted_heights_sit_just_under_cu_multiples(torch, width):
         n = lbm.lbm_get_workgroups(sim.ctx)
         k = -(-n // ncu)
         assert n <= k * ncu
-        if h > 1:
+        if h > tune.MIN_HEIGHT:
             tune.apply(sim, width, h - 1)
             assert lbm.lbm_get_workgroups(sim.ctx) > k * ncu, (h, n)
     sim.close()
@@ -400,37 +400,52 @@ def test_strip_width_does_not_change_results(torch, nx, ny, walls):
 
 def test_density_calls_follow_the_state(torch):
     """The step moves only populations; the calls that read densities compute those
-    of the current state: after steps, a force evaluation (which uses the scratch
-    density buffer) and a recorded window, the fields equal those of a second
-    context into which the same populations were imported.  Strips wider than a
-    workgroup of eight wavefronts covers (506 output columns) are refused."""
+    of the current state (a recording writes them itself).  A context taken
+    through steps, a force evaluation (which uses a scratch density buffer), a
+    recorded window and changes of strip plan (uniform, balanced) stays bitwise
+    equal to one stepped plainly, and its fields equal those of a context into
+    which the same populations were imported.  Strips wider than a workgroup of
+    eight wavefronts covers (506 output columns) are refused."""
     say("density calls")
     w = dataclasses.replace(W.droplet(nx=96, ny=40, radius=10), walls=1, rho_wall=(0.03, 1.0),
                             g=((1e-5, 0.0), (1e-5, 0.0)))
     a = lbm.Sim([lbm.workload_instance(w)])
     b = lbm.Sim([lbm.workload_instance(w)])
+    c = lbm.Sim([lbm.workload_instance(w)])
     try:
-        def same_fields():
+        def check(n):
+            c.step(n)
+            assert torch.equal(a.populations(), c.populations())
             b.set_populations(a.populations())
             fa, fb = a.fields(), b.fields()
-            return all(torch.equal(x, y) for x, y in zip(fa, fb))
+            assert all(torch.equal(x, y) for x, y in zip(fa, fb))
         a.step(5)
-        assert same_fields()
+        check(5)
         rho = a.fields()[0].contiguous()
         F = torch.empty((2, 2, 40, 96), dtype=torch.float32, device=rho.device)
         lbm.lbm_forces(a.ctx, 0, rho.data_ptr(), F.data_ptr())
-        assert same_fields()
+        a.step(3)
+        check(3)
         store = torch.empty((3, lbm.lbm_record_floats(a.ctx, 0)), dtype=torch.float32, device=rho.device)
         lbm.lbm_record(a.ctx, 0, 3, store.data_ptr())
-        assert same_fields()
+        check(3)
+        lbm.lbm_set_tiling(a.ctx, 5)
         a.step(16 + 3)  # a graph replay and eager steps
-        assert same_fields()
+        check(19)
+        lbm.lbm_set_balance(a.ctx, 2)
+        a.step(7)
+        check(7)
+        lbm.lbm_set_strip_width(a.ctx, 40)
+        lbm.lbm_set_tiling(a.ctx, 2)
+        a.step(4)
+        check(4)
         lbm.lbm_set_strip_width(a.ctx, 506)
         with pytest.raises(lbm.LBMError):
             lbm.lbm_set_strip_width(a.ctx, 507)
     finally:
         a.close()
         b.close()
+        c.close()
 
 
 def test_batched_balanced_plan_equals_uniform(torch):

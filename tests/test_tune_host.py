@@ -44,7 +44,7 @@ def test_fitted_heights_are_the_smallest_within_each_multiple(monkeypatch, ny, s
         return strips * -(-ny // h)
 
     want = set()
-    for k in range(1, 5):
+    for k in range(1, tune.FIT_KMAX + 1):
         ok = [h for h in range(tune.MIN_HEIGHT, max(ny, tune.MIN_HEIGHT) + 1) if wg(h) <= k * ncu]
         if ok:
             want.add(min(ok))
