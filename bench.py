@@ -49,6 +49,12 @@ DOMINANT = "k_fused_step"
 # the kernel sources they were measured on.
 MEASURED_TRAFFIC = {"src_sha256_16": "e86abe41d0bed219",
                     "plans": {(58, 74, 0): (160251.8 * 2.0 * 1024, 295557.5 * 1024),
+                              (58, 76, 0): (160906.6 * 2.0 * 1024, 295693.1 * 1024),
+                              (58, 78, 0): (160902.8 * 2.0 * 1024, 295661.8 * 1024),
+                              (58, 80, 0): (159643.6 * 2.0 * 1024, 295677.1 * 1024),
+                              (506, 41, 0): (170375.4 * 2.0 * 1024, 295425.9 * 1024),
+                              (250, 37, 0): (172945.3 * 2.0 * 1024, 296246.4 * 1024),
+                              (122, 48, 0): (168346.0 * 2.0 * 1024, 296727.3 * 1024),
                               (58, 64, 0): (163035.2 * 2.0 * 1024, 297303.5 * 1024),
                               (48, 90, 0): (159362.1 * 2.0 * 1024, 294912.0 * 1024),
                               (112, 52, 0): (167344.0 * 2.0 * 1024, 294913.7 * 1024),
