@@ -5,13 +5,14 @@ G2 move both components together) and the relaxation times of Eq. 1
 (arXiv:1806.06943).  An objective J (pressure jump, flow rate, momentum,
 mass; see ``lbm.OBJECTIVES``) of the state after a number of steps is
 differentiated in reverse mode with checkpoint-and-recompute: the forward
-pass keeps the state at the start of each window of steps; the backward pass
-re-runs each window forward from its checkpoint, storing its states, and
-applies the library's adjoint step (``lbm_adjoint_step``) backwards through
-the window.  The re-run of the window before runs meanwhile, in a second
-library context on a second stream fed by a second host thread, into the
-other of two state stores (events order each store's reuse), so the two
-latency-bound passes overlap.
+pass keeps the state at the start of each window of steps and records the
+states of the last window as it goes; the backward pass re-runs each earlier
+window forward from its checkpoint, storing its states, and applies the
+library's adjoint step (``lbm_adjoint_step``) backwards through the window.
+The re-run of the window before runs meanwhile, in a second library context
+on a second stream fed by a second host thread, into the other of two state
+stores (events order each store's reuse), so the two latency-bound passes
+overlap.
 Memory: one state per window boundary plus two windows of states.
 
 Argument marshalling and bookkeeping only: the step, the adjoint step and the
@@ -51,6 +52,8 @@ class Problem:
         self.shape = (2, 9, p.ny, p.nx)
         self.nodes = p.nx * p.ny
         self._store = None
+        self._forwards = 0
+        self._last_intact = False
 
     def theta(self) -> np.ndarray:
         return self.sim.theta(0)
@@ -63,33 +66,50 @@ class Problem:
             s += n
         return out
 
+    def _stores(self):
+        """The two window stores of states (allocated once, for windows of up to
+        `window` steps)."""
+        m = min(self.window, max(self.steps, 1))
+        if self._store is None or self._store.shape[1] < m:
+            t = self.torch
+            self._store = t.empty((2, m, lbm.lbm_record_floats(self.rec.ctx, 0)), dtype=t.float32,
+                                  device=self.sim.device)
+        return self._store
+
     def forward(self, theta):
         """J at theta; returns (J, saved) where saved feeds ``backward``."""
         t = self.torch
         self.sim.set_theta(theta)
         self.sim.set_populations(self.f0)
         ckpts = []
-        for _, n in self._windows():
+        wins = self._windows()
+        for w, (_, n) in enumerate(wins):
             c = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
             self.sim.populations_into(c)
             ckpts.append(c)
-            self.sim.step(n)
+            if w == len(wins) - 1:
+                # the last window's states go straight to the store its adjoint
+                # sweep reads, so the backward pass need not re-run it
+                lbm.lbm_record(self.sim.ctx, 0, n, self._stores()[w % 2].data_ptr())
+            else:
+                self.sim.step(n)
         fT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
         self.sim.populations_into(fT)
         lamT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
         J, direct = self.sim.adjoint_seed(self.objective, fT, lamT)
-        return J, (np.asarray(theta, dtype=np.float64).copy(), ckpts, lamT, direct)
+        self._forwards += 1  # names the forward pass whose last window the store holds
+        self._last_intact = True
+        return J, (np.asarray(theta, dtype=np.float64).copy(), ckpts, lamT, direct, self._forwards)
 
     def backward(self, saved):
         """(dJ/dtheta as numpy float64[5], dJ/df(0) as a device tensor)."""
         t = self.torch
-        theta, ckpts, lamT, direct = saved
+        theta, ckpts, lamT, direct, token = saved
+        # the store still holds this forward pass's last window unless another
+        # forward pass or the re-runs of an earlier backward pass wrote over it
+        last_kept = token == self._forwards and self._last_intact
         self.sim.set_theta(theta)
-        m = min(self.window, max(self.steps, 1))
-        if self._store is None or self._store.shape[1] < m:
-            self._store = t.empty((2, m, lbm.lbm_record_floats(self.rec.ctx, 0)), dtype=t.float32,
-                                  device=self.sim.device)
-        S = self._store
+        S = self._stores()
         grad = t.zeros(5, dtype=t.float64, device=self.sim.device)
         lam = lamT.clone()
         tmp = t.empty_like(lam)
@@ -99,6 +119,8 @@ class Problem:
         # the checkpoints and the seed come from the adjoint context's stream
         rec.stream.wait_stream(adj.stream)
         nw = len(wins)
+        if nw >= 3:  # window nw - 3 re-runs into the last window's store
+            self._last_intact = False
         recorded = [t.cuda.Event() for _ in range(nw)]  # window w re-run into S[w % 2]
         released = [t.cuda.Event() for _ in range(nw)]  # sweep of window w done with it
         queued_rec = [threading.Event() for _ in range(nw)]
@@ -118,8 +140,9 @@ class Problem:
                         if failed:
                             return
                         rec.stream.wait_event(released[w + 2])
-                    rec.set_populations(ckpts[w])
-                    lbm.lbm_record(rec.ctx, 0, wins[w][1], S[w % 2].data_ptr())
+                    if w < nw - 1 or not last_kept:  # else recorded by the forward pass
+                        rec.set_populations(ckpts[w])
+                        lbm.lbm_record(rec.ctx, 0, wins[w][1], S[w % 2].data_ptr())
                     recorded[w].record(rec.stream)
                     queued_rec[w].set()
             except BaseException as e:  # re-raised by the caller

@@ -209,6 +209,31 @@ def test_gradient_does_not_depend_on_the_window(torch, which):
         assert np.abs(g - out[0][1]).max() <= 1e-12 * np.abs(out[0][1]).max(), (g, out[0][1])
 
 
+def test_backward_keeps_to_its_own_forward_pass(torch):
+    """The forward pass records its last window for the backward pass; a backward
+    pass of an earlier forward pass, or a second backward pass of the same one
+    after the store was reused, re-runs that window instead: the gradients equal
+    those of a plain forward + backward bit for bit."""
+    say("stale store")
+    d = droplet_instance(48, 48, 0, R=12, g=1e-5)
+    for window in (30, 45):  # three windows (the last one's store is reused) and two
+        prob = AD.Problem(d, steps=90, objective="dp", window=window)
+        th = prob.theta()
+        th2 = th.copy()
+        th2[2] *= 1.01
+        J1, g1, l1 = prob.value_and_grad(th)
+        _, s1 = prob.forward(th)
+        prob.forward(th2)
+        for _ in range(2):
+            g, lam = prob.backward(s1)
+            assert np.array_equal(g, g1) and torch.equal(lam, l1), window
+        _, s3 = prob.forward(th)
+        for _ in range(2):  # the recorded window, then (three windows) a re-run
+            g, lam = prob.backward(s3)
+            assert np.array_equal(g, g1) and torch.equal(lam, l1), window
+        prob.close()
+
+
 def test_autograd_function_and_finite_differences(torch):
     say("autograd")
     d = droplet_instance(48, 48, 0, R=12, g=1e-5)
