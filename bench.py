@@ -244,8 +244,8 @@ def cpu_baseline(w, budget_s=15.0, steps=0):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU path is "
-              "design-only in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library has no "
+              "multi-GPU path (its sharding is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

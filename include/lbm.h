@@ -48,7 +48,7 @@ extern "C" {
 #define LBM_EINVAL (-1)       /* bad argument: sizes, tau <= 0.5, NULL, short buffer */
 #define LBM_EHIP (-2)         /* HIP runtime failure                                 */
 #define LBM_ENONFINITE (-3)   /* a reduction saw NaN or Inf in the state             */
-#define LBM_EUNSUPPORTED (-4) /* valid request that this build does not provide      */
+#define LBM_EUNSUPPORTED (-4) /* valid request that the library does not provide    */
 
 typedef struct lbm_ctx lbm_ctx;
 
