@@ -75,3 +75,16 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
     # null context handles
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_destroy(None) == lbm.LBM_EINVAL
+
+
+def test_largest_lattice_is_accepted_and_the_next_is_refused():
+    """Byte offsets inside a population buffer must stay below 2^31, the range of
+    the buffer descriptors the step addresses it with: 18 x ny x pitch floats (pitch
+    = nx rounded up to 64) plus 64 of padding.  At nx = 64 the last accepted height
+    is 466033."""
+    lbm.lbm_workspace_bytes([_ok_params(nx=64, ny=466033)])
+    lbm.lbm_workspace_bytes([_ok_params(nx=4096, ny=4096)])
+    for nx, ny in ((64, 466034), (5461, 5461), (1, 1 << 30)):
+        with pytest.raises(lbm.LBMError) as ei:
+            lbm.lbm_workspace_bytes([_ok_params(nx=nx, ny=ny)])
+        assert ei.value.code == lbm.LBM_EINVAL and "too large" in str(ei.value), (nx, ny)
