@@ -258,6 +258,49 @@ def test_spinodal_full_size_sampled_nodes(torch):
         assert abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] < 1e-6
 
 
+def test_largest_lattice_sampled_nodes(torch):
+    """The largest lattice the library accepts at nx = 64 (466033 rows: population
+    byte offsets up to 2 GiB less 3 KiB inside one buffer), walled, with a layer and
+    droplets of A, under a one-wavefront and a two-wavefront strip plan: sampled nodes
+    of step t+1, the last rows included, against the oracle's single-node step of the
+    GPU state at t; FP64 mass."""
+    nx, ny = 64, 466033
+    say("largest lattice", nx, ny)
+    rng = np.random.default_rng(5)
+    yy, xx = np.arange(ny)[:, None], np.arange(nx)[None, :]
+    A = (((yy >= ny - 40) & (yy < ny - 20)) | ((xx - 32) ** 2 + (yy - 20) ** 2 <= 100) |
+         ((xx - 20) ** 2 + (yy - ny // 2) ** 2 <= 144))
+    A = np.broadcast_to(A, (ny, nx))
+    cp = dict(G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.7), walls=1, rho_wall=(0.03, 1.0),
+              g=((1e-5, 0.0), (1e-5, 0.0)))
+    inst = dict(nx=nx, ny=ny, rhoA=np.where(A, 1.0, 0.03) + rng.uniform(-1e-3, 1e-3, (ny, nx)),
+                rhoB=np.where(A, 0.03, 1.0) + rng.uniform(-1e-3, 1e-3, (ny, nx)), **cp)
+    p = O.Params(nx=nx, ny=ny, **cp)
+    nodes = [(0, ny - 1), (63, ny - 1), (31, ny - 2), (5, ny - 3), (17, ny - 30), (0, 0), (63, 0),
+             (32, 20), (20, ny // 2), (44, ny // 2 + 11)] + \
+            [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(10)]
+    for cols, h in ((58, 74), (122, 512)):
+        sim = lbm.Sim([inst])
+        try:
+            lbm.lbm_set_strip_width(sim.ctx, cols)
+            lbm.lbm_set_tiling(sim.ctx, h)
+            obs0, _ = sim.observables()
+            sim.step(3)
+            f = sim.populations_full()
+            sim.step(1)
+            f1 = sim.populations_full()
+            for x, y in nodes:
+                want = O.step_at(p, f, x, y)
+                assert np.abs(f1[:, :, y, x] - want).max() < 2e-7, (cols, x, y)
+            del f, f1
+            sim.step(4)
+            obs1, _ = sim.observables()
+            for k in range(2):
+                assert abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] < 1e-6
+        finally:
+            sim.close()
+
+
 @pytest.mark.parametrize("ratio", [0.5, 4.0])
 def test_emulsion_full_size_sampled_nodes(torch, ratio):
     """4096x512 walled emulsion (200 droplets, g_x = 1e-6, nu_A/nu_B = ratio) under the
