@@ -216,6 +216,27 @@ def test_graph_replay_equals_launches_and_is_deterministic(torch):
     assert np.array_equal(c.populations().cpu().numpy(), fa)
 
 
+def test_zero_step_calls_change_nothing(torch):
+    """Empty work: zero steps, a recording of zero steps (no store needed) and an
+    adjoint run of zero steps leave the state, the step count and lambda as they were."""
+    w = W.droplet(nx=40, ny=24, radius=6, couplings=W.COUPLINGS_PAPER)
+    sim = lbm.Sim([lbm.workload_instance(w)])
+    try:
+        sim.step(5)
+        f0, n0 = sim.populations().clone(), sim.steps_done
+        sim.step(0)
+        lbm.lbm_record(sim.ctx, 0, 0, 0)
+        lam = torch.randn((2, 9, 24, 40), dtype=torch.float32, device=f0.device)
+        lam0, tmp = lam.clone(), torch.empty_like(lam)
+        grad = torch.zeros(5, dtype=torch.float64, device=f0.device)
+        lbm.lbm_adjoint_run(sim.ctx, 0, 0, 0, lam.data_ptr(), tmp.data_ptr(), grad.data_ptr())
+        torch.cuda.synchronize()
+        assert torch.equal(sim.populations(), f0) and sim.steps_done == n0
+        assert torch.equal(lam, lam0) and not grad.any()
+    finally:
+        sim.close()
+
+
 def test_batched_instances_equal_single_runs(torch):
     """One launch over uneven instances gives each instance's single-run result bitwise."""
     ws = [W.droplet(nx=64, ny=64, radius=10, couplings=W.COUPLINGS_PAPER),
