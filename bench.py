@@ -4,30 +4,40 @@ Workload: spinodal decomposition on a 2048 x 2048 periodic lattice,
 rho_A = 0.5 + U(-0.05, 0.05) per node (seeded), rho_B = 1 - rho_A,
 couplings (G_AB, G_1, G_2) = (0.405, -9.0, 8.1), tau = (1.0, 0.55), FP32 arithmetic
 and storage.  One step advances both components of every node (one lattice
-update, LU); the timed region replays the captured step loop with the inputs
-resident in HBM, plus one FP64 observable pass (mass and finiteness guard)
-per 1000 steps.
+update, LU).  After W warm-up steps the step graphs of both state parities are
+captured (lbm_prepare), then the timed region is exactly K steps on the
+context's stream between HIP events, with the inputs resident in HBM: graph
+replays of 16 steps plus single launches for the rest, nothing else.  One FP64
+observable pass (mass drift, finiteness) runs before and after it and is
+timed on its own.
 
 Prints ONE JSON line with MLUPS, the HBM roofline of the dominant kernel
 (HIP-event timing on the context's stream), a measured copy-kernel ceiling
 and the CPU oracle's rate on a bounded sample of the same workload.  Beside
 it, on the same GPU:
   * "batched": 96 uneven static-droplet instances (24 each of 64^2, 128^2,
-    192^2, 256^2) advanced by one launch per step; aggregate MLUPS;
+    192^2, 256^2) advanced by one launch per step for their 5000 steps;
+    aggregate MLUPS and, per instance, the relative error of the Laplace
+    pressure jump against the FP64 oracle's (stored expected values);
   * "adjoint": the 512 x 512 droplet array (16 droplets, R = 20, g_x = 1e-6):
     plain forward MLUPS, and forward + reverse-mode gradient of the pressure
     jump with respect to (G1, G2, G_AB, tau_A, tau_B) with checkpoints every
     200 steps, as MLUPS of the simulated steps, plus the adjoint kernels'
-    timings and algorithmic bandwidth.
+    timings and algorithmic bandwidth;
+  * "emulsion": the walled 4096 x 512 emulsion (200 droplets, R = 16,
+    g_x = 1e-6) at viscosity ratios nu_A / nu_B in {0.5, 1, 2, 4}: MLUPS and
+    the relative effective viscosity Q(0) / Q(Phi) after 50000 steps.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--batched-steps B] [--adjoint-steps A]
+                       [--batched-steps B] [--adjoint-steps A] [--emulsion-steps E]
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -97,7 +107,9 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="strip height (0: autotune)")
     ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 58)")
     ap.add_argument("--balance", type=int, default=0, help="with --width: workgroups per CU")
-    ap.add_argument("--batched-steps", type=int, default=1000, help="0 skips the batched form")
+    ap.add_argument("--batched-steps", type=int, default=5000, help="0 skips the batched form")
+    ap.add_argument("--emulsion-steps", type=int, default=50000,
+                    help="0 skips the emulsion viscosity-ratio sweep")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint form")
     ap.add_argument("--adjoint-window", type=int, default=200)
     return ap.parse_args()
@@ -124,17 +136,47 @@ def timed(torch, stream, fn):
     return e0.elapsed_time(e1)
 
 
+def golden_batched_laplace():
+    """Oracle (FP64) Laplace observables of the 96-instance workload after its
+    5000 steps, per instance, as written by tests/golden/make_oracle_golden.py."""
+    path = os.path.join(ROOT, "tests", "golden", "batched_laplace_oracle.txt")
+    if not os.path.exists(path):
+        return None
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = line.split()
+            rows[int(v[0])] = {"R": float(v[2]), "dp": float(v[3]), "gamma": float(v[4])}
+    return rows
+
+
+BATCHED_ORACLE_STEPS = 5000
+
+
 def bench_batched(torch, lbm, tune, W, steps):
-    """96 uneven instances in one context: one launch per step for all."""
+    """96 uneven instances in one context: one launch per step for all, from the
+    initial state; after the workload's 5000 steps the per-instance Laplace
+    pressure jump is compared with the oracle's."""
     ws = W.batched()
     sim = lbm.Sim([lbm.workload_instance(w) for w in ws], device="cuda:0")
     tuning = tune.tune(sim, use_cache=False)
     nodes = sum(w.nx * w.ny for w in ws)
-    sim.step(100)
+    sim.prepare()
     ms = timed(torch, sim.stream, lambda: sim.step(steps))
     obs, _ = sim.observables()
     prof = dict(lbm.lbm_profile_step(sim.ctx, 50))
     k_ms = prof["k_fused_step"]
+    lap = None
+    gold = golden_batched_laplace() if steps == BATCHED_ORACLE_STEPS else None
+    if gold is not None and len(gold) == len(ws):
+        err = np.array([abs(o["dp"] - gold[n]["dp"]) / abs(gold[n]["dp"]) for n, o in enumerate(obs)])
+        errR = np.array([abs(o["R_eff"] - gold[n]["R"]) / gold[n]["R"] for n, o in enumerate(obs)])
+        lap = {"steps": steps, "vs": "FP64 oracle, same initial fields (tests/golden)",
+               "dp_rel_err_max": float(err.max()), "dp_rel_err_median": float(np.median(err)),
+               "R_eff_rel_err_max": float(errR.max()),
+               "dp_rel_err_per_instance": [float(f"{e:.3g}") for e in err]}
     out = {"workload": "96 static droplets, 24 each of 64^2/128^2/192^2/256^2, R 8-40, "
                        "G2 in [7.0, 8.5], G1 = -1 - G2, G_AB = 3.0, tau_A/tau_B in {0.6, 1.0, 1.6}",
            "instances": len(ws), "nodes": nodes, "steps": steps,
@@ -142,8 +184,47 @@ def bench_batched(torch, lbm, tune, W, steps):
            "ms_per_step": round(ms / steps, 5), "strip_height": tuning,
            "kernel_ms": round(k_ms, 5),
            "alg_gbps": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9, 1),
+           "roofline_frac": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "laplace_error": lap,
            "all_finite": all(o["finite"] for o in obs)}
     sim.close()
+    return out
+
+
+def bench_emulsion(torch, lbm, tune, W, steps, ratios=(0.5, 1.0, 2.0, 4.0)):
+    """The walled 4096 x 512 emulsion (200 droplets of R = 16, g_x = 1e-6 on both
+    components) at each viscosity ratio nu_A / nu_B: MLUPS of `steps` steps from
+    the initial state, the flow rate Q, and the relative effective viscosity
+    mu_r = Q(Phi = 0) / Q(Phi) (Sec. III D) against the droplet-free channel at
+    the same parameters and step count."""
+    out = {"workload": "emulsion 4096x512, walls, 200 droplets R=16, g_x=1e-6, couplings "
+                       "(3.0, -7.4, 6.4), tau_B = 1, tau_A = 0.5 + 0.5 nu_A/nu_B",
+           "steps": steps, "ratios": {}}
+    plan = None
+    for r in ratios:
+        runs = {}
+        for phi, nd in (("phi", 200), ("zero", 0)):
+            w = W.emulsion(tau_ratio=r, ndrop=nd, steps=steps)
+            sim = lbm.Sim([lbm.workload_instance(w)], device="cuda:0")
+            if plan is None:
+                t = tune.tune(sim, use_cache=False)
+                plan = {k: t.get(k) for k in ("width", "best", "balance")}
+            else:
+                tune.apply(sim, plan["width"], plan["best"], plan["balance"])
+            sim.prepare()
+            ms = timed(torch, sim.stream, lambda: sim.step(steps))
+            obs, _ = sim.observables()
+            runs[phi] = (ms, obs[0], w)
+            sim.close()
+        ms, o, w = runs["phi"]
+        q0 = runs["zero"][1]["flow_rate"]
+        out["ratios"][str(r)] = {
+            "tau": list(w.tau), "M_paper": round(1.0 / r, 4),
+            "mlups": round(w.nx * w.ny * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 5),
+            "Q": o["flow_rate"], "Q_phi0": q0, "mu_r": q0 / o["flow_rate"],
+            "all_finite": bool(o["finite"] and runs["zero"][1]["finite"])}
+    out["strip_plan"] = plan
     return out
 
 
@@ -266,32 +347,33 @@ def main():
     else:
         tuning = tune.tune(sim, use_cache=False)
 
-    # warm-up (captures the step graph)
+    # warm-up, then capture the step graphs of both state parities, so that
+    # the timed region replays graphs (or launches) only
     sim.step(a.warmup)
+    sim.prepare()
     obs0, _ = sim.observables()
     torch.cuda.synchronize()
 
-    # timed region: K steps, observables every 1000 steps
+    # timed region: exactly K steps on the context's stream between HIP events
     st = sim.stream
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(st)
-    done = 0
-    while done < a.steps:
-        n = min(1000, a.steps - done)
-        sim.step(n)
-        done += n
-        if done % 1000 == 0 or done == a.steps:
-            sim.observables()
+    sim.step(a.steps)
     ev1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = ev0.elapsed_time(ev1)
     ms_per_step = ms_total / a.steps
     mlups = N * a.steps / (ms_total * 1e-3) / 1e6
+
+    # one FP64 observable pass (density pass, fields, reductions, D2H), timed
+    # on its own outside the stepping
+    o0 = time.perf_counter()
     obs1, _ = sim.observables()
+    obs_ms = (time.perf_counter() - o0) * 1e3
 
     # per-kernel durations on the context's stream (HIP events)
     prof = dict(lbm.lbm_profile_step(sim.ctx, 100))
@@ -317,6 +399,7 @@ def main():
 
     batched = bench_batched(torch, lbm, tune, W, a.batched_steps) if a.batched_steps > 0 else None
     adj = bench_adjoint(torch, lbm, W, a.adjoint_steps, a.adjoint_window) if a.adjoint_steps > 0 else None
+    emul = bench_emulsion(torch, lbm, tune, W, a.emulsion_steps) if a.emulsion_steps > 0 else None
 
     cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
     traffic = measured_traffic(lbm.lbm_get_strip_width(sim.ctx), lbm.lbm_get_tiling(sim.ctx),
@@ -353,10 +436,12 @@ def main():
         "frac_of_copy_ceiling": round(achieved / copy_gbps, 4),
         "strip_height": tuning,
         "mass_drift_fp32": mass_drift,
+        "observables_ms": round(obs_ms, 3),
         "wall_s": round(wall, 3),
         "cpu_baseline": cpu,
         "batched": batched,
         "adjoint": adj,
+        "emulsion": emul,
     }
     print(json.dumps(out), flush=True)
     sim.close()

@@ -122,6 +122,14 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
  * state with one density pass, once per state. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
+/* Capture the step graphs that lbm_step replays (one per parity of the
+ * state, 16 steps each) now, without running them; otherwise the first
+ * lbm_step of 16 or more steps from each parity captures its graph.  Lets a
+ * caller keep capture and instantiation out of a timed or latency-bound
+ * region.  Changes no state; the graphs stay valid until a strip-plan call
+ * discards them. */
+int lbm_prepare(lbm_ctx *ctx);
+
 /* Time steps taken since lbm_init (or the last lbm_set_populations). */
 int64_t lbm_steps_done(const lbm_ctx *ctx);
 

@@ -119,7 +119,10 @@ class Problem:
         # the checkpoints and the seed come from the adjoint context's stream
         rec.stream.wait_stream(adj.stream)
         nw = len(wins)
-        if nw >= 3:  # window nw - 3 re-runs into the last window's store
+        # the store of the last window is written over when window nw - 3
+        # re-runs into it, or when this pass re-runs its own last window
+        # there (its forward pass is not the one whose window the store holds)
+        if nw >= 3 or not last_kept:
             self._last_intact = False
         recorded = [t.cuda.Event() for _ in range(nw)]  # window w re-run into S[w % 2]
         released = [t.cuda.Event() for _ in range(nw)]  # sweep of window w done with it

@@ -57,7 +57,8 @@ struct Layout {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// Work of the fused step: segments {inst, X0, Y0, wo | ho << 16} and, per
+// Work of the fused step: segments {inst, X0, Y0, wo | ho << 16} (both
+// fields unsigned 16-bit: wo <= 506, ho <= 65535) and, per
 // workgroup g, the range first[g] .. first[g+1]-1 of segments it advances.
 struct StripPlan {
     std::vector<int4> segs;
@@ -85,6 +86,11 @@ std::vector<int2> column_strips(int nx, int W)
 
 constexpr int NXCD = 8;  // XCDs of the chip; workgroup g is dealt to XCD g % 8
 
+// width and height of a segment in one word, as unsigned 16-bit fields (a
+// height of 32768 or more sets the word's sign bit; the kernel decodes the
+// word as unsigned)
+int pack_wh(int wo, int ho) { return (int)((uint32_t)wo | ((uint32_t)ho << 16)); }
+
 // Every segment of a plan fits a strip of nw wavefronts: its lanes cover
 // the output columns, a collided halo column and HALO stencil columns on
 // each side (the fused step assumes this for its LDS ring).
@@ -108,7 +114,7 @@ StripPlan plan_uniform(const lbm_params *p, int n, int H, int W)
         const int nc = ceil_div(p[i].ny, H);
         for (int c = 0; c < nc; ++c) {
             const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
-            for (const int2 &cs : cols) tab.push_back(make_int4(i, cs.x, y0, cs.y | ((y1 - y0) << 16)));
+            for (const int2 &cs : cols) tab.push_back(make_int4(i, cs.x, y0, pack_wh(cs.y, y1 - y0)));
         }
     }
     const int T = (int)tab.size(), q = ceil_div(T, NXCD);
@@ -163,7 +169,7 @@ StripPlan plan_balanced(const lbm_params *p, int n, int W, int G)
             const int64_t uend = ubase + (U.y1 - U.y0);
             const int64_t e = std::min(b, uend);
             const int ys = U.y0 + (int)(a - ubase), ho = (int)(e - a);
-            share[l].push_back(make_int4(U.inst, U.x0, ys, U.wo | (ho << 16)));
+            share[l].push_back(make_int4(U.inst, U.x0, ys, pack_wh(U.wo, ho)));
             a = e;
         }
     }
@@ -534,6 +540,16 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps)
     if (rc != LBM_OK) return rc;
     if (nsteps > 0) ctx->rho_ok[0] = ctx->rho_ok[1] = false;
     ctx->steps += nsteps;
+    return LBM_OK;
+}
+
+int lbm_prepare(lbm_ctx *ctx)
+{
+    CTX_CHECK(ctx);
+    for (int par = 0; par < 2; ++par) {
+        int rc = ensure_graph(ctx, par);
+        if (rc != LBM_OK) return rc;
+    }
     return LBM_OK;
 }
 

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     // arithmetic parameters copied once: the buffer stores below could
     // otherwise alias them
     const KPar P = kpar(G);
-    const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = t.w >> 16;
+    const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = (int)((uint32_t)t.w >> 16);
     const int L = (int)threadIdx.x;
     const int l = L & 63, wv = L >> 6;
     const int nx = G.nx, ny = G.ny, walls = G.walls;

@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_init.argtypes = [P(vp), P(lbm_params), ctypes.c_int32, P(ctypes.c_double),
                                P(ctypes.c_double), vp, ctypes.c_uint64, vp]
         L.lbm_step.argtypes = [vp, ctypes.c_int64]
+        L.lbm_prepare.argtypes = [vp]
         L.lbm_steps_done.argtypes = [vp]
         L.lbm_steps_done.restype = ctypes.c_int64
         L.lbm_observables.argtypes = [vp, P(lbm_obs), P(ctypes.c_double)]
@@ -181,6 +182,10 @@ def lbm_init(params, rhoA0: np.ndarray, rhoB0: np.ndarray, workspace_ptr: int,
 
 def lbm_step(ctx, nsteps: int):
     _check(lib().lbm_step(ctx, int(nsteps)), ctx)
+
+
+def lbm_prepare(ctx):
+    _check(lib().lbm_prepare(ctx), ctx)
 
 
 def lbm_steps_done(ctx) -> int:
@@ -359,6 +364,10 @@ class Sim:
     # --------------------------------------------------------------- stepping
     def step(self, n: int = 1):
         lbm_step(self.ctx, n)
+
+    def prepare(self):
+        """Capture the step graphs of both state parities now (see lbm_prepare)."""
+        lbm_prepare(self.ctx)
 
     @property
     def steps_done(self) -> int:

@@ -24,6 +24,7 @@ from . import lbm
 
 CANDIDATES = (2, 3, 4, 6, 8, 12, 16, 24, 32, 40, 48, 64)
 MIN_HEIGHT = 2  # the smallest strip height lbm_set_tiling accepts
+MAX_HEIGHT = 65535  # and the largest
 # (output columns per strip): one wavefront per strip, balanced / aligned,
 # then strips of 2, 4 and 8 wavefronts, balanced / aligned
 WIDTHS = (58, 48, 122, 112, 250, 240, 506, 496)
@@ -71,7 +72,7 @@ def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX) -> list:
     """For k = 1..kmax the smallest uniform strip height at which the launch has at
     most k * ncu workgroups (the count falls as the height grows)."""
     hmin = MIN_HEIGHT
-    hmax = max(max(p.ny for p in sim.params), hmin)
+    hmax = min(max(max(p.ny for p in sim.params), hmin), MAX_HEIGHT)
     out = set()
     for k in range(1, kmax + 1):
         target = k * ncu

@@ -216,7 +216,9 @@ def test_backward_keeps_to_its_own_forward_pass(torch):
     those of a plain forward + backward bit for bit."""
     say("stale store")
     d = droplet_instance(48, 48, 0, R=12, g=1e-5)
-    for window in (30, 45):  # three windows (the last one's store is reused) and two
+    # three windows (the last one's store is reused), two, and one window
+    # (steps <= window)
+    for window in (30, 45, 90):
         prob = AD.Problem(d, steps=90, objective="dp", window=window)
         th = prob.theta()
         th2 = th.copy()
@@ -231,6 +233,16 @@ def test_backward_keeps_to_its_own_forward_pass(torch):
         for _ in range(2):  # the recorded window, then (three windows) a re-run
             g, lam = prob.backward(s3)
             assert np.array_equal(g, g1) and torch.equal(lam, l1), window
+        # an older forward pass's backward pass re-runs its last window into the
+        # store that holds the newer pass's: the newer backward pass must not
+        # then take that store as its own
+        _, g2, l2 = prob.value_and_grad(th2)
+        _, sa = prob.forward(th)
+        _, sb = prob.forward(th2)
+        g, lam = prob.backward(sa)
+        assert np.array_equal(g, g1) and torch.equal(lam, l1), window
+        g, lam = prob.backward(sb)
+        assert np.array_equal(g, g2) and torch.equal(lam, l2), window
         prob.close()
 
 

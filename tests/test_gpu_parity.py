@@ -437,6 +437,30 @@ def test_strip_height_does_not_change_results(torch):
         assert np.array_equal(f, ref), h
 
 
+def test_strip_heights_past_15_bits(torch):
+    """A segment height is packed beside its width as an unsigned 16-bit field:
+    chunks of 32768 rows and more (the word's sign bit set) advance the same
+    rows as short chunks, bit for bit, on a tall, narrow walled lattice."""
+    ny = 40000
+    say("tall chunks", 16, ny)
+    rA = np.full((ny, 16), 0.03)
+    rA[ny // 4: 3 * ny // 4, 4:12] = 1.0
+    rA += 1e-3 * np.random.default_rng(3).random((ny, 16))
+    inst = dict(nx=16, ny=ny, rhoA=rA, rhoB=1.03 - rA, G_AB=3.0, G1=-7.4, G2=6.4,
+                tau=(1.0, 0.6), walls=1, rho_wall=(0.03, 1.0), g=((1e-5, 0.0), (1e-5, 0.0)))
+    ref = None
+    for h in (16, 32768, 40000, 65535):
+        sim = lbm.Sim([inst])
+        lbm.lbm_set_tiling(sim.ctx, h)
+        assert lbm.lbm_get_workgroups(sim.ctx) == -(-ny // h), h
+        sim.step(5)
+        f = sim.populations().cpu().numpy()
+        sim.close()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), h
+
+
 @pytest.mark.parametrize("nx,ny,walls", [(200, 96, 1), (600, 40, 0), (37, 21, 1)])
 def test_strip_width_does_not_change_results(torch, nx, ny, walls):
     """Strips of 1 to 8 wavefronts, balanced or 64-byte aligned, uniform chunks or an
