@@ -139,6 +139,22 @@ int64_t lbm_steps_done(const lbm_ctx *ctx);
  * (after filling out) if any instance holds NaN or Inf. */
 int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar);
 
+/* For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, hosts that forbid allocation after start-up): the observables
+ * of lbm_observables (same kernels, same results bit for bit) into host
+ * out[n_inst], without ubar, allocating nothing on the host or the device.
+ * The FP64 reduction partials, the per-instance results and the packed
+ * records live in a static device array of the library, 4 MiB per GPU (held
+ * from the first lbm_init on that GPU until the process ends), whose device
+ * address lbm_init resolves.  A context whose 12 * (total rows) + 46 *
+ * n_inst doubles exceed 2^19 gets LBM_EINVAL.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap in time on one GPU (contexts on
+ * different streams or host threads) race and must be serialised by the
+ * caller.  Each call writes every scratch word it reads, so nothing carries
+ * over from an earlier call.  Synchronises the stream; LBM_ENONFINITE as
+ * lbm_observables. */
+int lbm_observables_noalloc(lbm_ctx *ctx, lbm_obs *out);
+
 /* Density and barycentric velocity (Eq. 7) fields of instance inst, FP32,
  * into device buffers rho[2][ny][nx] and u[2][ny][nx] (either may be NULL).
  * Asynchronous. */

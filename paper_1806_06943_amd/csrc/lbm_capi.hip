@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,40 @@ constexpr int MIN_WIDTH = 16;    // narrowest strip the workspace is sized for
 constexpr int DEFAULT_WIDTH = SWO;
 
 thread_local std::string g_init_error;
+
+// Reduction scratch of lbm_observables_noalloc: FP64 row partials, per-instance
+// results and the packed lbm_obs records of one call.  One copy per GPU,
+// held until the process ends.  Host code never passes the array's name to
+// a kernel or a copy: it uses the device address that hipGetSymbolAddress
+// gives for the current device (scratch_address, resolved by lbm_init).
+constexpr uint64_t SCRATCH_DOUBLES = (uint64_t)1 << 19;  // 4 MiB
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array (device dev must be current).
+hipError_t scratch_address(int dev, double **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// doubles of scratch that lbm_observables_noalloc needs for this context
+uint64_t noalloc_doubles(int nrows, int ninst)
+{
+    const uint64_t obs_words = (sizeof(lbm_obs) + 7) / 8;
+    return (uint64_t)nrows * NQR + (uint64_t)ninst * (NRES + obs_words);
+}
 
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
@@ -315,6 +350,7 @@ struct lbm_ctx {
     // rho[par] holds the densities of the state in f[par] (the plain step
     // does not write them; ensure_rho computes them when a kernel reads them)
     bool rho_ok[2] = {false, false};
+    double *scratch = nullptr;  // this device's scratch array (lbm_observables_noalloc)
     std::string err;
 };
 
@@ -412,10 +448,19 @@ int lbm_init(lbm_ctx **out, const lbm_params *params, int32_t n_inst, const doub
     d.nrows = L.nrows;
     {
         int dev = 0, ncu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
+        hipError_t de = hipGetDevice(&dev);
+        if (de == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             ncu > 0)
             ctx->ncu = ncu;
+        // this device's reduction scratch for lbm_observables_noalloc, with
+        // the context's device current
+        if (de == hipSuccess) de = scratch_address(dev, &ctx->scratch);
+        if (de != hipSuccess) {
+            std::string m = std::string("scratch address: ") + hipGetErrorString(de);
+            delete ctx;
+            return fail(nullptr, LBM_EHIP, m);
+        }
     }
     StripPlan plan = plan_uniform(params, n_inst, ctx->chunk, ctx->width);
     if (!plan_fits(plan, strip_waves(ctx->width))) {
@@ -563,7 +608,7 @@ int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar)
     if (rc) return rc;
     hipStream_t st = ctx->stream;
     const double margin = 12.0;  // outer pressure shell starts 12 lattice units beyond R_eff
-    hipError_t e = launch_observables(ctx->dev, ctx->par, margin, st);
+    hipError_t e = launch_observables(ctx->dev, ctx->par, margin, ctx->dev.part, ctx->dev.res, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "observable kernels");
     std::vector<double> res((size_t)NRES * ctx->n_inst);
     HIP_TRY(ctx, hipMemcpyAsync(res.data(), ctx->dev.res, sizeof(double) * res.size(),
@@ -609,6 +654,34 @@ int lbm_observables(lbm_ctx *ctx, lbm_obs *out, double *ubar)
         row += ctx->params[i].ny;
     }
     if (bad) return fail(ctx, LBM_ENONFINITE, "non-finite density or velocity in the state");
+    return LBM_OK;
+}
+
+int lbm_observables_noalloc(lbm_ctx *ctx, lbm_obs *out)
+{
+    CTX_CHECK(ctx);
+    if (!out) return fail(ctx, LBM_EINVAL, "null output");
+    const Dev &d = ctx->dev;
+    if (noalloc_doubles(d.nrows, d.ninst) > SCRATCH_DOUBLES)
+        return fail(ctx, LBM_EINVAL,
+                    "lbm_observables_noalloc: " + std::to_string(d.nrows) + " rows and " +
+                        std::to_string(d.ninst) + " instances need " +
+                        std::to_string(noalloc_doubles(d.nrows, d.ninst) * 8) +
+                        " bytes of scratch, more than its " + std::to_string(SCRATCH_DOUBLES * 8));
+    int rc = ensure_rho(ctx);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    double *part = ctx->scratch;
+    double *res = part + (uint64_t)d.nrows * NQR;
+    lbm_obs *packed = (lbm_obs *)(res + (uint64_t)d.ninst * NRES);
+    const double margin = 12.0;  // as lbm_observables
+    hipError_t e = launch_observables(d, ctx->par, margin, part, res, st);
+    if (e == hipSuccess) e = launch_obs_pack(d, res, packed, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "observable kernels");
+    HIP_TRY(ctx, hipMemcpyAsync(out, packed, sizeof(lbm_obs) * d.ninst, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int i = 0; i < d.ninst; ++i)
+        if (!out[i].finite) return fail(ctx, LBM_ENONFINITE, "non-finite density or velocity in the state");
     return LBM_OK;
 }
 

@@ -54,7 +54,12 @@ hipError_t launch_fields_out(const Dev &d, int inst, float *rho, float *u, hipSt
 hipError_t launch_export(const Dev &d, int inst, int par, float *f, hipStream_t st);
 hipError_t launch_import(const Dev &d, int inst, int par, const float *f, hipStream_t st);
 hipError_t launch_forces(const Dev &d, int inst, int par, const float *rho, float *F, hipStream_t st);
-hipError_t launch_observables(const Dev &d, int par, double margin, hipStream_t st);
+// the reduction partials go to part[nrows][NQR], the per-instance results
+// to res[ninst][NRES] (the workspace's, or any other device buffer)
+hipError_t launch_observables(const Dev &d, int par, double margin, double *part, double *res,
+                              hipStream_t st);
+// per-instance results res[ninst][NRES] as lbm_obs records out[ninst] (device)
+hipError_t launch_obs_pack(const Dev &d, const double *res, lbm_obs *out, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t st);
 
 // ------------------------------------------------------------------ adjoint

@@ -1030,21 +1030,61 @@ hipError_t launch_forces(const Dev &d, int inst, int par, const float *rho, floa
 
 // fields, then three row passes with their per-instance final passes; the
 // per-row u_x sums (slot 6 of pass 1) stay untouched by passes 2 and 3.
-hipError_t launch_observables(const Dev &d, int par, double margin, hipStream_t st)
+hipError_t launch_observables(const Dev &d, int par, double margin, double *part, double *res,
+                              hipStream_t st)
 {
     hipError_t e = launch_fields(d, par, st);
     if (e != hipSuccess) return e;
-    k_red_rows1<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, par, d.part);
+    k_red_rows1<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, par, part);
     LAUNCH_CHECK();
-    k_red_final1<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, d.part, d.res);
+    k_red_final1<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, part, res);
     LAUNCH_CHECK();
-    k_red_rows2<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, d.res, d.part);
+    k_red_rows2<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, res, part);
     LAUNCH_CHECK();
-    k_red_final2<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, d.part, d.res);
+    k_red_final2<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, part, res);
     LAUNCH_CHECK();
-    k_red_rows3<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, d.res, margin, d.part);
+    k_red_rows3<<<d.nrows, RT, 0, st>>>(d.insts, d.rows, res, margin, part);
     LAUNCH_CHECK();
-    k_red_final3<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, d.part, d.res);
+    k_red_final3<<<d.ninst, RT, 0, st>>>(d.insts, d.row0s, part, res);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+// The per-instance results as lbm_obs records, one thread per instance (the
+// same assignments lbm_observables makes on the host).
+__global__ void k_obs_pack(const double *__restrict__ res, int ninst, lbm_obs *__restrict__ out)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= ninst) return;
+    const double *R = res + (int64_t)i * NRES;
+    lbm_obs o;
+    o.mass[0] = R[RES_MASSA];
+    o.mass[1] = R[RES_MASSB];
+    o.mom_raw[0] = R[RES_PX];
+    o.mom_raw[1] = R[RES_PY];
+    o.mom_bary[0] = R[RES_JX];
+    o.mom_bary[1] = R[RES_JY];
+    o.max_speed = R[RES_UMAX];
+    o.rho_a_max = R[RES_AMAX];
+    o.rho_a_min = R[RES_AMIN];
+    o.flow_rate = R[RES_Q];
+    o.R_eff = R[RES_R];
+    o.cx = R[RES_CX];
+    o.cy = R[RES_CY];
+    o.p_in = R[RES_PIN];
+    o.p_out = R[RES_POUT];
+    o.dp = R[RES_DP];
+    o.gamma = R[RES_GAMMA];
+    o.width = R[RES_W];
+    o.n_in = (int64_t)R[RES_NIN];
+    o.n_out = (int64_t)R[RES_NOUT];
+    o.finite = R[RES_BAD] == 0.0 && isfinite(R[RES_MASSA]) && isfinite(R[RES_MASSB]);
+    out[i] = o;
+}
+
+hipError_t launch_obs_pack(const Dev &d, const double *res, lbm_obs *out, hipStream_t st)
+{
+    k_obs_pack<<<(d.ninst + 63) / 64, 64, 0, st>>>(res, d.ninst, out);
     LAUNCH_CHECK();
     return hipSuccess;
 }

@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_steps_done.argtypes = [vp]
         L.lbm_steps_done.restype = ctypes.c_int64
         L.lbm_observables.argtypes = [vp, P(lbm_obs), P(ctypes.c_double)]
+        L.lbm_observables_noalloc.argtypes = [vp, P(lbm_obs)]
         L.lbm_fields.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.lbm_get_populations.argtypes = [vp, ctypes.c_int32, vp]
         L.lbm_set_populations.argtypes = [vp, ctypes.c_int32, vp]
@@ -203,6 +204,14 @@ def lbm_observables(ctx, n_inst: int, total_rows: int | None = None, check: bool
     if check or rc not in (LBM_OK, LBM_ENONFINITE):
         _check(rc, ctx)
     return rc, [o.as_dict() for o in out], ubar
+
+
+def lbm_observables_noalloc(ctx, n_inst: int, check: bool = True):
+    out = (lbm_obs * n_inst)()
+    rc = lib().lbm_observables_noalloc(ctx, out)
+    if check or rc not in (LBM_OK, LBM_ENONFINITE):
+        _check(rc, ctx)
+    return rc, [o.as_dict() for o in out]
 
 
 def lbm_fields(ctx, inst: int, rho_ptr: int | None, u_ptr: int | None):
