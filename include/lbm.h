@@ -170,7 +170,7 @@ int lbm_fields(lbm_ctx *ctx, int32_t inst, float *rho_dev, float *u_dev);
  *   problem), sum_k rho_k cs^2 delta + K^tau of the original model for the
  *   velocity shift (density gradients by central differences).
  * If line_tension is not NULL it receives (1/ny) sum_{x,y} (P_xx - P_yy)
- * (FP64): the line tension of Eqs. 16, 17 for interfaces orthogonal to x
+ * (FP64): the line tension of Eqs. 15, 16 for interfaces orthogonal to x
  * (per interface pair it is the overall line tension gamma_f; one interface
  * gives gamma), and the stream is synchronised; otherwise asynchronous.
  * Overwrites the instance's field scratch. */

@@ -8,12 +8,12 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lbm_oracle.c", "lbm_oracle_adjoint.c"]
+SOURCES = ["lbm_oracle.c"]
 TARGET = os.path.join(HERE, "_lbm_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
     cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c11",
            "-Wall", "-Wextra", "-shared", "-fPIC", "-o", TARGET + ".tmp"] + srcs + ["-lm"]
     if verbose:

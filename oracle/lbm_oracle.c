@@ -850,7 +850,7 @@ double ora_objective(const ora_params *p, const double *f, int which, double *la
  * is used: it equals the interaction part of the bulk equation of state
  * (Eq. 11) in a uniform state, and its sum over a flat interface is the
  * total virial of the pairs that cross it, which is what the surface-tension
- * integral (Eq. 16) needs.  For the velocity-shift forcing the kinetic part
+ * integral (Eq. 15) needs.  For the velocity-shift forcing the kinetic part
  * is the paper's explicit sum_k rho_k cs^2 delta + K^tau (the tau-dependent
  * terms), with tau = (rho_A tau_A + rho_B tau_B) / rho, F the total force
  * and the density gradients by central differences (a reading: the paper

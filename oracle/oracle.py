@@ -291,12 +291,12 @@ def pressure(p: Params, f: np.ndarray) -> np.ndarray:
 
 
 def line_tension(P: np.ndarray) -> float:
-    """Eq. 16 / Eq. 17 for interfaces orthogonal to x: sum_x (P_xx - P_yy), mean over y."""
+    """Eq. 15 / Eq. 16 for interfaces orthogonal to x: sum_x (P_xx - P_yy), mean over y."""
     return float((P[0] - P[1]).sum(axis=1).mean())
 
 
 def disjoining_pressure(h: np.ndarray, gf: np.ndarray, gamma: float) -> np.ndarray:
-    """Eq. 19 from gamma_f(h) on a grid of h: s = gamma_f - 2 gamma,
+    """Eq. 18 from gamma_f(h) on a grid of h: s = gamma_f - 2 gamma,
     Pi(h) = s(h)/h - int_h^inf s/h'^2 dh' (trapezoid rule, s beyond the last h taken as 0)."""
     h = np.asarray(h, dtype=np.float64)
     s = np.asarray(gf, dtype=np.float64) - 2.0 * gamma
@@ -396,3 +396,31 @@ def max_speed(fl: dict) -> float:
     """Maximum |u| of the barycentric velocity (Appendix, spurious currents)."""
     u = fl["u"]
     return float(np.sqrt(u[0] ** 2 + u[1] ** 2).max())
+
+
+def radial_correlation(phi: np.ndarray, rmax: int | None = None):
+    """Radially averaged two-point correlation of a periodic field:
+    C(r) = <phi(x) phi(x + d)>_{x, |d| in [r - 1/2, r + 1/2)} - <phi>^2, normalised
+    by C(0) (Wiener-Khinchin: the autocorrelation by FFT, a library step)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    ny, nx = phi.shape
+    d = phi - phi.mean()
+    ac = np.fft.ifft2(np.abs(np.fft.fft2(d)) ** 2).real / d.size
+    dy = np.minimum(np.arange(ny), ny - np.arange(ny))[:, None]
+    dx = np.minimum(np.arange(nx), nx - np.arange(nx))[None, :]
+    rbin = np.rint(np.sqrt(dx * dx + dy * dy)).astype(int)
+    rmax = min(nx, ny) // 2 if rmax is None else rmax
+    sums = np.bincount(rbin.ravel(), weights=ac.ravel(), minlength=rmax + 1)[:rmax + 1]
+    counts = np.bincount(rbin.ravel(), minlength=rmax + 1)[:rmax + 1]
+    C = sums / np.maximum(counts, 1)
+    return C / C[0]
+
+
+def domain_size(phi: np.ndarray) -> float:
+    """Mean domain size of a demixing pattern: the first zero of the radial
+    correlation of phi, linearly interpolated between lattice distances."""
+    C = radial_correlation(phi)
+    for r in range(1, len(C)):
+        if C[r] <= 0.0 < C[r - 1]:
+            return float(r - 1 + C[r - 1] / (C[r - 1] - C[r]))
+    return float("nan")

@@ -3,10 +3,11 @@
 // gather, the two-belt force from an LDS density tile and the FP32 collision.
 //
 // Storage: the state at time t is the post-streaming, pre-collision
-// populations f(t) as FP32 deviations f - w_i rho_ref, plus their density
-// deviations sum_i (f_i - w_i rho_ref), correctly rounded (double-buffered
-// with those of t+1).  The collision needs exactly that
-// rounded sum, so the step reads it instead of summing again.
+// populations f(t) as FP32 deviations f - w_i rho_ref.  Their density
+// deviations sum_i (f_i - w_i rho_ref), correctly rounded, are formed by the
+// step from the populations it loads (the collision needs exactly that
+// rounded sum); density buffers (double-buffered with those of t+1) are
+// written only for the kernels and calls that read densities.
 //
 // Layout: row-major rows; within a row the 18 populations q = 9 k + i of a
 // node are packed into vector planes of `pitch` nodes: four float4 planes

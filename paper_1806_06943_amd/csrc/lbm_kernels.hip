@@ -172,9 +172,9 @@ struct RingAccW {
 // 1 the velocity shift of the original model (momenta without F/2, BGK
 // towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
 // Reads f[par]; writes f[par ^ 1] and, with ovr.wrho, rho[par ^ 1].
-// Register budget: three waves per SIMD (168 VGPRs), which every strip
-// width meets without spilling although four rows of populations are live
-// across the collision.
+// Register budget: two waves per SIMD (at most 256 VGPRs; the kernel uses
+// about 211), which every strip width meets without spilling although four
+// rows of populations are live across the collision.
 template <int NW, int FS>
 __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     const KInst *__restrict__ insts, const int4 *__restrict__ segs, const int *__restrict__ first,

@@ -1,5 +1,5 @@
 // Pressure tensor of the two-range model (Sec. II B) and the line-tension
-// integral of a flat interface (Eqs. 16, 17), for gfx950.
+// integral of a flat interface (Eqs. 15, 16), for gfx950.
 //
 // P = P^int + P^kin per node.  P^int is the pair-sum (virial) form of the
 // pairwise lattice forces of Eqs. 8 and 9,

@@ -14,7 +14,7 @@
 
 * Pressure tensor (Sec. II B): the library's tensor and line tension against
   the oracle's; flat-interface gamma = 0.04 independent of M within 1.2 %
-  (Sec. III C); disjoining pressure (Eqs. 17-19) with the shapes of Fig. 3a.
+  (Sec. III C); disjoining pressure (Eqs. 16-18) with the shapes of Fig. 3a.
 * Droplet collisions (Sec. III C, Figs. 5-6): two equal droplets of A in B
   meeting head-on at Ca ~ 0.3 and We ~ 15 bounce back under the present model
   at M = 1 and M = 3 (the film of B between them survives); the single-range
@@ -210,7 +210,7 @@ def _film_instance(nx, ny, film, G1, G2, hi, lo):
 
 
 def test_disjoining_pressure_shapes_of_fig3a(torch):
-    """Eqs. 17-19 on films of B of thickness h between A (G_AB = 3.0), started at the
+    """Eqs. 16-18 on films of B of thickness h between A (G_AB = 3.0), started at the
     coexistence densities of a long wide-slab run: the single-range case
     (G_A1 = G_A2 = 0) has a negative disjoining pressure at small h, the two-range
     cases a positive peak, higher for lower G_A1 (Fig. 3a and its caption)."""

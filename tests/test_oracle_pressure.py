@@ -6,7 +6,7 @@
   (3.0, -7.4, 6.4) has gamma = 0.04 (Sec. III D, two printed digits).
 * The paper's central claim (Sec. III C): with the present forcing gamma is
   the same for viscosity ratios M = 1/10, 1, 10 within 1.2 %.
-* The integral route (Eq. 16) and the mechanical route (Laplace's law on a
+* The integral route (Eq. 15) and the mechanical route (Laplace's law on a
   droplet, bulk pressures of Eq. 11) give the same gamma.
 """
 import numpy as np
