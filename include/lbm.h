@@ -64,7 +64,10 @@ typedef struct {
                             common velocity (Eq. 5); LBM_FORCING_SHIFT (1): the velocity
                             shift of the original two-range model (its explicit form C^SC,
                             Sec. II A), for comparison.  All instances of a context use
-                            the same scheme.                                            */
+                            the same scheme.  The shift as Eq. 4 states it does not
+                            reproduce the original model's numbers of Sec. III C: at the
+                            emulsion couplings it is stable only for tau >= 1, where its
+                            surface tension is about 0.16, not 0.043.                  */
     double G_AB;         /* inter-species coupling of Eq. 9 (> 0 repulsive)             */
     double G1[2];        /* short-range coupling of Eq. 8 per component {A, B}          */
     double G2[2];        /* mid-range coupling of Eq. 8 per component {A, B}            */
