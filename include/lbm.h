@@ -238,6 +238,16 @@ int32_t lbm_get_balance(const lbm_ctx *ctx);
 /* Workgroups of one launch of the fused step under the current strip plan. */
 int32_t lbm_get_workgroups(const lbm_ctx *ctx);
 
+/* The same strip planner on the host, without a context or a device: for
+ * params[0..n_inst-1], strips of cols output columns, and either uniform
+ * chunks of chunk_rows rows (wgs = 0) or the balanced plan of exactly wgs
+ * workgroups (wgs in [1, 8192]; lbm_set_balance asks for wgs_per_cu times
+ * the compute units), *nwg receives the workgroups of one launch and, if
+ * nsegs is not NULL, *nsegs the segments they advance.  LBM_EINVAL for
+ * arguments lbm_set_tiling / lbm_set_strip_width / lbm_set_balance refuse. */
+int lbm_plan_workgroups(const lbm_params *params, int32_t n_inst, int32_t cols, int32_t chunk_rows,
+                        int32_t wgs, int32_t *nwg, int32_t *nsegs);
+
 /* ------------------------------------------------------------------------
  * Reverse-mode adjoint (gradients of objectives with respect to the state and
  * to theta = (G1, G2, G_AB, tau_A, tau_B), where G1 and G2 move the couplings

@@ -23,5 +23,18 @@ def build(verbose: bool = False) -> str:
     return TARGET
 
 
+def build_sanitized(target: str, verbose: bool = False) -> str:
+    """The same source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only; load it with the ASan runtime preloaded)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+           "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", target] + srcs + ["-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return target
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

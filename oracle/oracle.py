@@ -21,7 +21,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "_lbm_oracle.so")
+# LBM_ORACLE_SO selects another build of the same source (the sanitizer test
+# loads an address- and undefined-behaviour-sanitized one)
+_SO = os.environ.get("LBM_ORACLE_SO") or os.path.join(_HERE, "_lbm_oracle.so")
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)

@@ -25,6 +25,7 @@ import threading
 import numpy as np
 
 from . import lbm
+from . import trace
 
 
 class Problem:
@@ -84,15 +85,16 @@ class Problem:
         ckpts = []
         wins = self._windows()
         for w, (_, n) in enumerate(wins):
-            c = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
-            self.sim.populations_into(c)
-            ckpts.append(c)
-            if w == len(wins) - 1:
-                # the last window's states go straight to the store its adjoint
-                # sweep reads, so the backward pass need not re-run it
-                lbm.lbm_record(self.sim.ctx, 0, n, self._stores()[w % 2].data_ptr())
-            else:
-                self.sim.step(n)
+            with trace.range(f"forward window {w}"):
+                c = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
+                self.sim.populations_into(c)
+                ckpts.append(c)
+                if w == len(wins) - 1:
+                    # the last window's states go straight to the store its adjoint
+                    # sweep reads, so the backward pass need not re-run it
+                    lbm.lbm_record(self.sim.ctx, 0, n, self._stores()[w % 2].data_ptr())
+                else:
+                    self.sim.step(n)
         fT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
         self.sim.populations_into(fT)
         lamT = t.empty(self.shape, dtype=t.float32, device=self.sim.device)
@@ -144,8 +146,9 @@ class Problem:
                             return
                         rec.stream.wait_event(released[w + 2])
                     if w < nw - 1 or not last_kept:  # else recorded by the forward pass
-                        rec.set_populations(ckpts[w])
-                        lbm.lbm_record(rec.ctx, 0, wins[w][1], S[w % 2].data_ptr())
+                        with trace.range(f"re-run window {w}"):
+                            rec.set_populations(ckpts[w])
+                            lbm.lbm_record(rec.ctx, 0, wins[w][1], S[w % 2].data_ptr())
                     recorded[w].record(rec.stream)
                     queued_rec[w].set()
             except BaseException as e:  # re-raised by the caller
@@ -161,8 +164,9 @@ class Problem:
                 if failed:
                     break
                 adj.stream.wait_event(recorded[w])
-                lbm.lbm_adjoint_run(adj.ctx, 0, wins[w][1], S[w % 2].data_ptr(), lam.data_ptr(),
-                                    tmp.data_ptr(), grad.data_ptr())
+                with trace.range(f"adjoint window {w}"):
+                    lbm.lbm_adjoint_run(adj.ctx, 0, wins[w][1], S[w % 2].data_ptr(),
+                                        lam.data_ptr(), tmp.data_ptr(), grad.data_ptr())
                 released[w].record(adj.stream)
                 queued_adj[w].set()
         except BaseException as e:

@@ -593,22 +593,20 @@ __global__ __launch_bounds__(NTHREADS) void k_obj_lin(AdjPar A, const float *__r
 // not NULL, grad[0..4] += res[0..4].
 __global__ __launch_bounds__(256) void k_adj_final(AdjPar A, int nblocks, double *__restrict__ grad)
 {
-    __shared__ double red[256];
+    __shared__ double red[NPART * (256 / 64)];
+    double v[NPART];
+    int op[NPART];
     for (int j = 0; j < NPART; ++j) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += 256) s += A.part[(int64_t)b * NPART + j];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            A.res[j] = red[0];
-            if (grad && j < 5) grad[j] += red[0];
-        }
-        __syncthreads();
+        v[j] = 0.0;
+        op[j] = RED_SUM;
+        for (int b = threadIdx.x; b < nblocks; b += 256) v[j] += A.part[(int64_t)b * NPART + j];
     }
+    block_reduce<256>(v, op, red);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < NPART; ++j) {
+            A.res[j] = v[j];
+            if (grad && j < 5) grad[j] += v[j];
+        }
 }
 
 dim3 agrid(const AdjPar &A) { return dim3((A.nx + TX - 1) / TX, (A.ny + TY - 1) / TY); }

@@ -842,6 +842,29 @@ int32_t lbm_get_balance(const lbm_ctx *ctx) { return ctx ? ctx->balance : -1; }
 
 int32_t lbm_get_workgroups(const lbm_ctx *ctx) { return ctx ? ctx->dev.nwg : -1; }
 
+int lbm_plan_workgroups(const lbm_params *params, int32_t n_inst, int32_t cols, int32_t chunk_rows,
+                        int32_t wgs, int32_t *nwg, int32_t *nsegs)
+{
+    if (!params || !nwg || n_inst < 1) return fail(nullptr, LBM_EINVAL, "null argument or n_inst < 1");
+    for (int i = 0; i < n_inst; ++i) {
+        std::string m = check_params(params[i]);
+        if (!m.empty()) return fail(nullptr, LBM_EINVAL, "instance " + std::to_string(i) + ": " + m);
+    }
+    if (cols < MIN_WIDTH || cols > MAX_STRIP_COLS)
+        return fail(nullptr, LBM_EINVAL, "cols must be in [16, 506]");
+    if (wgs < 0 || wgs > MAX_WG) return fail(nullptr, LBM_EINVAL, "wgs must be in [0, 8192]");
+    if (wgs == 0 && (chunk_rows < MIN_CHUNK || chunk_rows > 65535))
+        return fail(nullptr, LBM_EINVAL, "chunk_rows must be in [2, 65535]");
+    StripPlan plan = wgs > 0 ? plan_balanced(params, n_inst, cols, wgs)
+                             : plan_uniform(params, n_inst, chunk_rows, cols);
+    if (!plan_fits(plan, strip_waves(cols))) return fail(nullptr, LBM_EINVAL, "strip wider than its workgroup");
+    if ((int)plan.segs.size() > max_strips(params, n_inst))
+        return fail(nullptr, LBM_EINVAL, "strip table overflow");
+    *nwg = (int32_t)plan.first.size() - 1;
+    if (nsegs) *nsegs = (int32_t)plan.segs.size();
+    return LBM_OK;
+}
+
 int32_t lbm_get_tiling(const lbm_ctx *ctx) { return ctx ? ctx->chunk : -1; }
 
 int lbm_destroy(lbm_ctx *ctx)

@@ -150,6 +150,44 @@ __device__ __forceinline__ float sum9(const float f[9])
     return (float)s;
 }
 
+// FP64 block reductions in a fixed order.  Each wavefront combines its 64
+// values by an xor butterfly: every step combines the same two operands on
+// both lanes of a pair, so all lanes end with the same bits and no barrier
+// is needed.  Lane 0 of each wavefront parks its result in LDS; after one
+// barrier thread 0 combines the wavefronts' results in wavefront order.  The
+// result is valid in thread 0.  Bitwise reproducible for a given block size.
+enum RedOp { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
+
+__device__ __forceinline__ double red_op(int op, double a, double b)
+{
+    return op == RED_SUM ? a + b : op == RED_MAX ? fmax(a, b) : fmin(a, b);
+}
+
+// v[q] (per thread) -> v[q] (thread 0) reduced with op[q]; lds holds
+// N * NT / 64 doubles
+template <int NT, int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], const int (&op)[N], double *lds)
+{
+    constexpr int NWV = NT / 64;
+    const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[q] = red_op(op[q], v[q], __shfl_xor(v[q], o, 64));
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) lds[q * NWV + wv] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double a = lds[q * NWV];
+            for (int w = 1; w < NWV; ++w) a = red_op(op[q], a, lds[q * NWV + w]);
+            v[q] = a;
+        }
+    __syncthreads();  // the LDS may be reused after the call
+}
+
 // LDS density tile: rho and psi of both components on the tile plus a halo
 // of 2, laid out [k][row][col] with (TX + 4) columns.
 struct Tile {

@@ -597,40 +597,18 @@ __global__ __launch_bounds__(NTHREADS) void k_forces(const KInst *__restrict__ i
 }
 
 // ------------------------------------------------------------------ FP64 reductions
-// One block per (instance, row); every quantity is accumulated in FP64 in a
-// fixed order (per-thread strided loop, then an LDS tree), so results are
-// bitwise reproducible.
+// One block per (instance, row) for the row passes, one per instance for the
+// final passes; every quantity is accumulated in FP64 in a fixed order (a
+// per-thread strided loop, then block_reduce: wavefront butterflies and one
+// LDS pass in wavefront order), so results are bitwise reproducible.
 constexpr int RT = 256;  // threads of reduction blocks
 
-__device__ __forceinline__ double tree_sum(double v, double *s)
+// per-thread partials of the rows [row0, row0 + nrow) of quantity q
+__device__ __forceinline__ double rows_acc(const double *part, int row0, int nrow, int q, int op)
 {
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = RT / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-        __syncthreads();
-    }
-    const double r = s[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ double tree_max(double v, double *s)
-{
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = RT / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + off]);
-        __syncthreads();
-    }
-    const double r = s[0];
-    __syncthreads();
-    return r;
-}
-
-__device__ __forceinline__ double tree_min(double v, double *s)
-{
-    return -tree_max(-v, s);
+    double a = op == RED_SUM ? 0.0 : op == RED_MAX ? -INFINITY : INFINITY;
+    for (int r = threadIdx.x; r < nrow; r += RT) a = red_op(op, a, part[(int64_t)(row0 + r) * NQR + q]);
+    return a;
 }
 
 // pass 1 per row: masses and population momentum from the populations;
@@ -639,7 +617,7 @@ __global__ __launch_bounds__(RT) void k_red_rows1(const KInst *__restrict__ inst
                                                    const int2 *__restrict__ rows, int par,
                                                    double *__restrict__ part)
 {
-    __shared__ double s[RT];
+    __shared__ double s[11 * (RT / 64)];
     const int2 r = rows[blockIdx.x];
     const KInst &P = insts[r.x];
     const int y = r.y;
@@ -672,38 +650,14 @@ __global__ __launch_bounds__(RT) void k_red_rows1(const KInst *__restrict__ inst
         amax = fmax(amax, ra);
         amin = fmin(amin, ra);
     }
-    double *o = part + (int64_t)blockIdx.x * NQR;
-    const double v0 = tree_sum(mA, s), v1 = tree_sum(mB, s), v2 = tree_sum(px, s),
-                 v3 = tree_sum(py, s), v4 = tree_sum(jx, s), v5 = tree_sum(jy, s),
-                 v6 = tree_sum(su, s), v7 = tree_max(umax, s), v8 = tree_max(amax, s),
-                 v9 = tree_min(amin, s), v10 = tree_sum(bad, s);
+    double v[11] = {mA, mB, px, py, jx, jy, su, umax, amax, amin, bad};
+    constexpr int op[11] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM,
+                            RED_SUM, RED_MAX, RED_MAX, RED_MIN, RED_SUM};
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
-        o[0] = v0; o[1] = v1; o[2] = v2; o[3] = v3; o[4] = v4; o[5] = v5;
-        o[6] = v6; o[7] = v7; o[8] = v8; o[9] = v9; o[10] = v10;
+        double *o = part + (int64_t)blockIdx.x * NQR;
+        for (int q = 0; q < 11; ++q) o[q] = v[q];
     }
-}
-
-// fixed-order sum over the rows of one instance: thread t takes rows
-// t, t + RT, ... in order, then the LDS tree combines the threads.
-__device__ double rows_sum(const double *part, int row0, int nrow, int q, double *s)
-{
-    double a = 0;
-    for (int r = threadIdx.x; r < nrow; r += RT) a += part[(int64_t)(row0 + r) * NQR + q];
-    return tree_sum(a, s);
-}
-
-__device__ double rows_max(const double *part, int row0, int nrow, int q, double *s)
-{
-    double a = -INFINITY;
-    for (int r = threadIdx.x; r < nrow; r += RT) a = fmax(a, part[(int64_t)(row0 + r) * NQR + q]);
-    return tree_max(a, s);
-}
-
-__device__ double rows_min(const double *part, int row0, int nrow, int q, double *s)
-{
-    double a = INFINITY;
-    for (int r = threadIdx.x; r < nrow; r += RT) a = fmin(a, part[(int64_t)(row0 + r) * NQR + q]);
-    return tree_min(a, s);
 }
 
 // final pass 1: one block per instance
@@ -712,31 +666,29 @@ __global__ __launch_bounds__(RT) void k_red_final1(const KInst *__restrict__ ins
                                                     const double *__restrict__ part,
                                                     double *__restrict__ res)
 {
-    __shared__ double s[RT];
+    __shared__ double s[11 * (RT / 64)];
     const int inst = blockIdx.x;
     const KInst &P = insts[inst];
     const int row0 = row0s[inst], nrow = P.ny;
     const double N = (double)P.nx * (double)P.ny;
     double *R = res + (int64_t)inst * NRES;
-    const double mA = rows_sum(part, row0, nrow, 0, s), mB = rows_sum(part, row0, nrow, 1, s);
-    const double px = rows_sum(part, row0, nrow, 2, s), py = rows_sum(part, row0, nrow, 3, s);
-    const double jx = rows_sum(part, row0, nrow, 4, s), jy = rows_sum(part, row0, nrow, 5, s);
-    const double su = rows_sum(part, row0, nrow, 6, s);
-    const double um = rows_max(part, row0, nrow, 7, s);
-    const double am = rows_max(part, row0, nrow, 8, s), an = rows_min(part, row0, nrow, 9, s);
-    const double bad = rows_sum(part, row0, nrow, 10, s);
+    constexpr int op[11] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM,
+                            RED_SUM, RED_MAX, RED_MAX, RED_MIN, RED_SUM};
+    double v[11];
+    for (int q = 0; q < 11; ++q) v[q] = rows_acc(part, row0, nrow, q, op[q]);
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
-        R[RES_MASSA] = N * (double)P.rho_ref[0] + mA;
-        R[RES_MASSB] = N * (double)P.rho_ref[1] + mB;
-        R[RES_PX] = px;
-        R[RES_PY] = py;
-        R[RES_JX] = jx;
-        R[RES_JY] = jy;
-        R[RES_Q] = su / (double)P.nx;
-        R[RES_UMAX] = um;
-        R[RES_AMAX] = am;
-        R[RES_AMIN] = an;
-        R[RES_BAD] = bad;
+        R[RES_MASSA] = N * (double)P.rho_ref[0] + v[0];
+        R[RES_MASSB] = N * (double)P.rho_ref[1] + v[1];
+        R[RES_PX] = v[2];
+        R[RES_PY] = v[3];
+        R[RES_JX] = v[4];
+        R[RES_JY] = v[5];
+        R[RES_Q] = v[6] / (double)P.nx;
+        R[RES_UMAX] = v[7];
+        R[RES_AMAX] = v[8];
+        R[RES_AMIN] = v[9];
+        R[RES_BAD] = v[10];
     }
 }
 
@@ -747,7 +699,7 @@ __global__ __launch_bounds__(RT) void k_red_rows2(const KInst *__restrict__ inst
                                                    const double *__restrict__ res,
                                                    double *__restrict__ part)
 {
-    __shared__ double s[RT];
+    __shared__ double s[3 * (RT / 64)];
     const int2 r = rows[blockIdx.x];
     const KInst &P = insts[r.x];
     const double rmin = res[(int64_t)r.x * NRES + RES_AMIN];
@@ -762,12 +714,14 @@ __global__ __launch_bounds__(RT) void k_red_rows2(const KInst *__restrict__ inst
         wc += v * cs;
         ws += v * sn;
     }
-    double *o = part + (int64_t)blockIdx.x * NQR;
-    const double a = tree_sum(w, s), b = tree_sum(wc, s), c = tree_sum(ws, s);
+    double v[3] = {w, wc, ws};
+    constexpr int op[3] = {RED_SUM, RED_SUM, RED_SUM};
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
-        o[0] = a;
-        o[1] = b;
-        o[2] = c;
+        double *o = part + (int64_t)blockIdx.x * NQR;
+        o[0] = v[0];
+        o[1] = v[1];
+        o[2] = v[2];
     }
 }
 
@@ -776,15 +730,12 @@ __global__ __launch_bounds__(RT) void k_red_final2(const KInst *__restrict__ ins
                                                     const double *__restrict__ part,
                                                     double *__restrict__ res)
 {
-    __shared__ double s[RT];
+    __shared__ double s[5 * (RT / 64)];
     const int inst = blockIdx.x;
     const KInst &P = insts[inst];
     const int row0 = row0s[inst], nrow = P.ny;
     double *R = res + (int64_t)inst * NRES;
-    const double W = rows_sum(part, row0, nrow, 0, s);
-    const double Wc = rows_sum(part, row0, nrow, 1, s);
-    const double Ws = rows_sum(part, row0, nrow, 2, s);
-    // y moments: row weights times cos/sin of the row angle
+    // x sums of the rows, then y moments: row weights times cos/sin of the row angle
     double yc = 0, ys = 0;
     const double k = 2.0 * M_PI / (double)P.ny;
     for (int rr = threadIdx.x; rr < nrow; rr += RT) {
@@ -794,8 +745,12 @@ __global__ __launch_bounds__(RT) void k_red_final2(const KInst *__restrict__ ins
         yc += v * cs;
         ys += v * sn;
     }
-    const double Yc = tree_sum(yc, s), Ys = tree_sum(ys, s);
+    double v[5] = {rows_acc(part, row0, nrow, 0, RED_SUM), rows_acc(part, row0, nrow, 1, RED_SUM),
+                   rows_acc(part, row0, nrow, 2, RED_SUM), yc, ys};
+    constexpr int op[5] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM, RED_SUM};
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
+        const double W = v[0], Wc = v[1], Ws = v[2], Yc = v[3], Ys = v[4];
         const double span = R[RES_AMAX] - R[RES_AMIN];
         const double area = span > 0 ? W / span : 0.0;
         double cx = atan2(Ws, Wc) * (double)P.nx / (2.0 * M_PI);
@@ -817,7 +772,7 @@ __global__ __launch_bounds__(RT) void k_red_rows3(const KInst *__restrict__ inst
                                                    const double *__restrict__ res,
                                                    double margin, double *__restrict__ part)
 {
-    __shared__ double s[RT];
+    __shared__ double s[4 * (RT / 64)];
     const int2 r = rows[blockIdx.x];
     const KInst &P = insts[r.x];
     const double *R = res + (int64_t)r.x * NRES;
@@ -840,14 +795,15 @@ __global__ __launch_bounds__(RT) void k_red_rows3(const KInst *__restrict__ inst
             nout += 1;
         }
     }
-    double *o = part + (int64_t)blockIdx.x * NQR;
-    const double a = tree_sum(pin, s), b = tree_sum(nin, s), c = tree_sum(pout, s),
-                 d = tree_sum(nout, s);
+    double v[4] = {pin, nin, pout, nout};
+    constexpr int op[4] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM};
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
-        o[0] = a;
-        o[1] = b;
-        o[2] = c;
-        o[3] = d;
+        double *o = part + (int64_t)blockIdx.x * NQR;
+        o[0] = v[0];
+        o[1] = v[1];
+        o[2] = v[2];
+        o[3] = v[3];
     }
 }
 
@@ -856,14 +812,17 @@ __global__ __launch_bounds__(RT) void k_red_final3(const KInst *__restrict__ ins
                                                     const double *__restrict__ part,
                                                     double *__restrict__ res)
 {
-    __shared__ double s[RT];
+    __shared__ double s[4 * (RT / 64)];
     const int inst = blockIdx.x;
     const KInst &P = insts[inst];
     const int row0 = row0s[inst], nrow = P.ny;
     double *R = res + (int64_t)inst * NRES;
-    const double pin = rows_sum(part, row0, nrow, 0, s), nin = rows_sum(part, row0, nrow, 1, s);
-    const double pout = rows_sum(part, row0, nrow, 2, s), nout = rows_sum(part, row0, nrow, 3, s);
+    double v[4];
+    constexpr int op[4] = {RED_SUM, RED_SUM, RED_SUM, RED_SUM};
+    for (int q = 0; q < 4; ++q) v[q] = rows_acc(part, row0, nrow, q, RED_SUM);
+    block_reduce<RT>(v, op, s);
     if (threadIdx.x == 0) {
+        const double pin = v[0], nin = v[1], pout = v[2], nout = v[3];
         const double a = nin > 0 ? pin / nin : NAN;
         const double b = nout > 0 ? pout / nout : NAN;
         R[RES_PIN] = a;

@@ -148,16 +148,12 @@ __global__ __launch_bounds__(NTHREADS) void k_pressure(const KInst *__restrict__
 __global__ __launch_bounds__(256) void k_pressure_final(const double *__restrict__ part, int n,
                                                         double *__restrict__ res)
 {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < n; b += 256) s += part[b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) res[0] = red[0];
+    __shared__ double red[256 / 64];
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < n; b += 256) v[0] += part[b];
+    constexpr int op[1] = {RED_SUM};
+    block_reduce<256>(v, op, red);
+    if (threadIdx.x == 0) res[0] = v[0];
 }
 
 }  // namespace

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbm_hip.so")
+# LBM_HIP_SO selects another build of the same sources (the sanitizer test
+# loads one whose host code is address- and undefined-behaviour-sanitized)
+LIB_PATH = os.environ.get("LBM_HIP_SO") or os.path.join(_PKG, "liblbm_hip.so")
 
 LBM_OK = 0
 LBM_EINVAL = -1
@@ -105,6 +107,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_balance.argtypes = [vp, ctypes.c_int32]
         L.lbm_get_balance.argtypes = [vp]
         L.lbm_get_balance.restype = ctypes.c_int32
+        L.lbm_plan_workgroups.argtypes = [P(lbm_params), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
+                                          P(ctypes.c_int32)]
         L.lbm_get_workgroups.argtypes = [vp]
         L.lbm_get_workgroups.restype = ctypes.c_int32
         L.lbm_get_strip_width.argtypes = [vp]
@@ -265,6 +270,15 @@ def lbm_set_balance(ctx, wgs_per_cu: int):
 
 def lbm_get_balance(ctx) -> int:
     return int(lib().lbm_get_balance(ctx))
+
+
+def lbm_plan_workgroups(params, cols: int, chunk_rows: int = 16, wgs: int = 0):
+    """(workgroups, segments) of a strip plan, planned on the host."""
+    arr = (lbm_params * len(params))(*params)
+    nwg, nseg = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lbm_plan_workgroups(arr, len(params), int(cols), int(chunk_rows), int(wgs),
+                                     ctypes.byref(nwg), ctypes.byref(nseg)))
+    return int(nwg.value), int(nseg.value)
 
 
 def lbm_get_workgroups(ctx) -> int:

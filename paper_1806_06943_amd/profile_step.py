@@ -1,0 +1,61 @@
+"""Launch the fused step of one workload under a given strip plan, for profilers.
+
+Builds the seeded workload (the same generators as the tests and the
+benchmark), applies the strip plan (or tunes it), then times `--launches`
+back-to-back launches of the step's kernel on the context's stream with HIP
+events (lbm_profile_step) and prints the plan, the workgroup count and the
+average launch time.  Under ``rocprofv3 --pmc ...`` every launch is one
+dispatch of the counters, so the per-dispatch averages describe this plan.
+
+    python -m paper_1806_06943_amd.profile_step --workload batched --width 58 --chunk 64
+"""
+from __future__ import annotations
+
+import argparse
+
+from . import lbm, tune
+from . import workloads as W
+
+
+def build(name: str):
+    if name == "batched":
+        ws = W.batched()
+    elif name == "spinodal":
+        ws = [W.spinodal()]
+    elif name == "emulsion":
+        ws = [W.emulsion()]
+    elif name == "adjoint_array":
+        ws = [W.adjoint_array()]
+    else:
+        raise ValueError(name)
+    return ws, lbm.Sim([lbm.workload_instance(w) for w in ws])
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--workload", default="batched",
+                    choices=("batched", "spinodal", "emulsion", "adjoint_array"))
+    ap.add_argument("--width", type=int, default=0, help="strip width (0: tune)")
+    ap.add_argument("--chunk", type=int, default=16, help="strip height with --width")
+    ap.add_argument("--balance", type=int, default=0, help="workgroups per CU with --width")
+    ap.add_argument("--launches", type=int, default=50)
+    a = ap.parse_args()
+    ws, sim = build(a.workload)
+    if a.width > 0:
+        tune.apply(sim, a.width, a.chunk, a.balance)
+    else:
+        t = tune.tune(sim, use_cache=False)
+        print(f"tuned: width {t['width']} height {t['best']} balance {t['balance']}", flush=True)
+    sim.step(20)
+    ms = dict(lbm.lbm_profile_step(sim.ctx, a.launches))["k_fused_step"]
+    nodes = sum(w.nx * w.ny for w in ws)
+    print(f"{a.workload}: {len(ws)} instances, {nodes} nodes, plan {lbm.lbm_get_strip_width(sim.ctx)} x "
+          f"{lbm.lbm_get_tiling(sim.ctx)} balance {lbm.lbm_get_balance(sim.ctx)}, "
+          f"{lbm.lbm_get_workgroups(sim.ctx)} workgroups: {ms:.5f} ms per launch, "
+          f"{nodes / (ms * 1e-3) / 1e6:.1f} MLUPS, {160.0 * nodes / (ms * 1e-3) / 1e9:.1f} GB/s at "
+          f"160 B per lattice update", flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1806_06943_amd import lbm
@@ -88,3 +89,41 @@ def test_largest_lattice_is_accepted_and_the_next_is_refused():
         with pytest.raises(lbm.LBMError) as ei:
             lbm.lbm_workspace_bytes([_ok_params(nx=nx, ny=ny)])
         assert ei.value.code == lbm.LBM_EINVAL and "too large" in str(ei.value), (nx, ny)
+
+
+def _ceil(a, b):
+    return -(-a // b)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_host_planner_counts(seed):
+    """Uniform plans: every column strip of every instance is cut into ceil(ny / H)
+    chunks, one workgroup each; column strips are ceil(nx / cols).  Balanced plans:
+    exactly the asked number of workgroups (at most one per strip-row)."""
+    r = np.random.default_rng(seed)
+    ps = [_ok_params(nx=int(r.integers(1, 700)), ny=int(r.integers(1, 300)), walls=int(r.integers(0, 2)))
+          for _ in range(int(r.integers(1, 7)))]
+    for cols in (16, 48, 58, 64, 112, 122, 240, 250, 496, 506):
+        for H in (2, 3, 16, 74, 65535):
+            n, nseg = lbm.lbm_plan_workgroups(ps, cols, H)
+            want = sum(_ceil(p.ny, H) * _ceil(p.nx, cols) for p in ps)
+            assert n == nseg == want, (cols, H)
+        strip_rows = sum(p.ny * _ceil(p.nx, cols) for p in ps)
+        for G in (1, 7, 256, 1024, 8192):
+            n, nseg = lbm.lbm_plan_workgroups(ps, cols, 0, G)
+            assert n == min(G, strip_rows) and nseg >= n, (cols, G)
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_plan_workgroups(ps, 15, 16)
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_plan_workgroups(ps, 58, 1)
+    with pytest.raises(lbm.LBMError):
+        lbm.lbm_plan_workgroups(ps, 58, 16, 8193)
+
+
+def test_host_planner_tall_chunks():
+    """Heights of 32768 and more (the sign bit of the packed segment word) plan
+    like any other height."""
+    p = [_ok_params(nx=64, ny=466033, walls=1)]
+    for H in (32767, 32768, 40000, 65535):
+        n, _ = lbm.lbm_plan_workgroups(p, 58, H)
+        assert n == _ceil(466033, H) * 2

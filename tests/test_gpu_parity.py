@@ -322,7 +322,7 @@ def test_largest_lattice_sampled_nodes(torch):
             sim.close()
 
 
-@pytest.mark.parametrize("ratio", [0.5, 4.0])
+@pytest.mark.parametrize("ratio", [0.5, 1.0, 2.0, 4.0])
 def test_emulsion_full_size_sampled_nodes(torch, ratio):
     """4096x512 walled emulsion (200 droplets, g_x = 1e-6, nu_A/nu_B = ratio) under the
     tuned strip plan: sampled nodes, wall rows and lattice edges included, of step t+1
