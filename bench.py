@@ -208,9 +208,9 @@ def bench_emulsion(torch, lbm, tune, W, steps, ratios=(0.5, 1.0, 2.0, 4.0)):
             sim = lbm.Sim([lbm.workload_instance(w)], device="cuda:0")
             if plan is None:
                 t = tune.tune(sim, use_cache=False)
-                plan = {k: t.get(k) for k in ("width", "best", "balance")}
+                plan = {k: t.get(k) for k in ("width", "best", "balance", "full_rows")}
             else:
-                tune.apply(sim, plan["width"], plan["best"], plan["balance"])
+                tune.apply(sim, plan["width"], plan["best"], plan["balance"], plan["full_rows"])
             sim.prepare()
             ms = timed(torch, sim.stream, lambda: sim.step(steps))
             obs, _ = sim.observables()
@@ -242,7 +242,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
     fwd.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
     for s in (prob.sim, prob.rec):  # forward context and window re-run context
-        tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0))
+        tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0),
+                   tuning.get("full_rows", 0))
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -271,7 +272,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     return {"workload": f"{w.nx}x{w.ny} periodic, 16 droplets R=20, g_x=1e-6, "
                         "couplings (3.0, -7.4, 6.4), tau (1.0, 0.6)",
             "steps": steps, "window": window, "objective": "J_dp (smooth pressure jump)",
-            "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance")},
+            "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance", "full_rows")},
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),
             "J": J, "grad_theta": {n: float(v) for n, v in zip(lbm.THETA_NAMES, g)},

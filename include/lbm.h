@@ -235,6 +235,18 @@ int32_t lbm_get_strip_width(const lbm_ctx *ctx);
 int lbm_set_balance(lbm_ctx *ctx, int32_t wgs_per_cu);
 int32_t lbm_get_balance(const lbm_ctx *ctx);
 
+/* Full-row plan (on = 1) for contexts whose lattice widths are all multiples
+ * of 64, at most 512: a group of nx / 64 wavefronts covers whole rows, every
+ * lane loading, colliding and writing one column of its own, so no column
+ * is read or collided twice; rows are cut into the uniform chunks of
+ * lbm_set_tiling, and chunks of equal height share workgroups of 1, 2, 4 or
+ * 8 wavefronts (the smallest that holds the widest lattice).  LBM_EUNSUPPORTED
+ * for other widths.  on = 0, lbm_set_strip_width and lbm_set_balance return
+ * to strips.  Results are bitwise identical for every plan.  Synchronises the
+ * stream and discards captured graphs. */
+int lbm_set_full_rows(lbm_ctx *ctx, int32_t on);
+int32_t lbm_get_full_rows(const lbm_ctx *ctx);
+
 /* Workgroups of one launch of the fused step under the current strip plan. */
 int32_t lbm_get_workgroups(const lbm_ctx *ctx);
 
@@ -242,11 +254,14 @@ int32_t lbm_get_workgroups(const lbm_ctx *ctx);
  * params[0..n_inst-1], strips of cols output columns, and either uniform
  * chunks of chunk_rows rows (wgs = 0) or the balanced plan of exactly wgs
  * workgroups (wgs in [1, 8192]; lbm_set_balance asks for wgs_per_cu times
- * the compute units), *nwg receives the workgroups of one launch and, if
- * nsegs is not NULL, *nsegs the segments they advance.  LBM_EINVAL for
- * arguments lbm_set_tiling / lbm_set_strip_width / lbm_set_balance refuse. */
+ * the compute units), or, with full_rows = 1, the full-row plan of chunks of
+ * chunk_rows rows (cols and wgs ignored), *nwg receives the workgroups of one
+ * launch and, if nsegs is not NULL, *nsegs the segments (full-row groups)
+ * they advance.  LBM_EINVAL for arguments lbm_set_tiling /
+ * lbm_set_strip_width / lbm_set_balance refuse, LBM_EUNSUPPORTED for a
+ * full-row plan of lattices lbm_set_full_rows refuses. */
 int lbm_plan_workgroups(const lbm_params *params, int32_t n_inst, int32_t cols, int32_t chunk_rows,
-                        int32_t wgs, int32_t *nwg, int32_t *nsegs);
+                        int32_t wgs, int32_t full_rows, int32_t *nwg, int32_t *nsegs);
 
 /* ------------------------------------------------------------------------
  * Reverse-mode adjoint (gradients of objectives with respect to the state and

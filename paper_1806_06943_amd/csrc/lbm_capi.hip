@@ -219,6 +219,81 @@ StripPlan plan_balanced(const lbm_params *p, int n, int W, int G)
     return P;
 }
 
+// Full-row plans: lattices whose width is a multiple of 64 are advanced by
+// groups of k = nx / 64 wavefronts covering whole rows.  0 if some instance
+// is not of that form or wider than eight wavefronts, else the workgroup
+// size in wavefronts (the smallest of 1, 2, 4, 8 that holds the widest).
+int fullrow_waves(const lbm_params *p, int n)
+{
+    int kmax = 0;
+    for (int i = 0; i < n; ++i) {
+        if (p[i].nx % 64 != 0 || p[i].nx > 8 * 64) return 0;
+        kmax = std::max(kmax, p[i].nx / 64);
+    }
+    return kmax <= 1 ? 1 : kmax <= 2 ? 2 : kmax <= 4 ? 4 : 8;
+}
+
+// Full-row plan for workgroups of NW wavefronts: every instance's rows cut
+// into ceil(ny / H) chunks of balanced height, one group of k = nx / 64
+// wavefronts each ({inst, first wavefront w0, Y0, k | ho << 16}).  Groups of
+// equal height share workgroups (best fit, widest first), so every group of a
+// workgroup runs the same number of rows; a workgroup's groups are its
+// segment range.  Workgroups are then ordered like the uniform plan's, so
+// that each XCD advances a run of neighbouring chunks.
+StripPlan plan_fullrow(const lbm_params *p, int n, int H, int NW)
+{
+    struct Grp {
+        int inst, k, y0, ho;
+    };
+    std::vector<Grp> grp;
+    for (int i = 0; i < n; ++i) {
+        const int nc = ceil_div(p[i].ny, H);
+        for (int c = 0; c < nc; ++c) {
+            const int y0 = (int)((int64_t)p[i].ny * c / nc), y1 = (int)((int64_t)p[i].ny * (c + 1) / nc);
+            grp.push_back({i, p[i].nx / 64, y0, y1 - y0});
+        }
+    }
+    // by height, then widest first (stable: instance and chunk order kept)
+    std::stable_sort(grp.begin(), grp.end(), [](const Grp &a, const Grp &b) {
+        return a.ho != b.ho ? a.ho > b.ho : a.k > b.k;
+    });
+    std::vector<std::vector<int4>> wgs;
+    std::vector<int> fill;
+    // open workgroups of the current height by free wavefronts
+    std::vector<std::vector<int>> open(NW + 1);
+    int cur_h = -1;
+    for (const Grp &g : grp) {
+        if (g.ho != cur_h) {
+            for (auto &o : open) o.clear();
+            cur_h = g.ho;
+        }
+        int w = -1;
+        for (int f = g.k; f <= NW && w < 0; ++f)
+            if (!open[f].empty()) {
+                w = open[f].back();
+                open[f].pop_back();
+            }
+        if (w < 0) {
+            w = (int)wgs.size();
+            wgs.emplace_back();
+            fill.push_back(0);
+        }
+        wgs[w].push_back(make_int4(g.inst, fill[w], g.y0, pack_wh(g.k, g.ho)));
+        fill[w] += g.k;
+        if (fill[w] < NW) open[NW - fill[w]].push_back(w);
+    }
+    const int T = (int)wgs.size(), q = ceil_div(T, NXCD);
+    StripPlan P;
+    for (int m = 0; m < q; ++m)
+        for (int j = 0; j < NXCD; ++j)
+            if (j * q + m < T) {
+                P.first.push_back((int)P.segs.size());
+                for (const int4 &e : wgs[j * q + m]) P.segs.push_back(e);
+            }
+    P.first.push_back((int)P.segs.size());
+    return P;
+}
+
 // segments a plan may need: uniform plans of any allowed width and height,
 // balanced plans of up to MAX_WG workgroups
 constexpr int MAX_WG = 8192;
@@ -346,6 +421,7 @@ struct lbm_ctx {
     int chunk = DEFAULT_CHUNK;
     int width = DEFAULT_WIDTH;
     int balance = 0;   // workgroups per CU of a balanced plan (0: uniform chunks)
+    int full_rows = 0; // 1: full-row plan of uniform chunks (lattice widths 64 k)
     int ncu = 256;     // compute units of the device
     // rho[par] holds the densities of the state in f[par] (the plain step
     // does not write them; ensure_rho computes them when a kernel reads them)
@@ -784,14 +860,18 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     return rc;
 }
 
-static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance)
+static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance, int full_rows = 0)
 {
-    StripPlan plan = balance > 0
-                         ? plan_balanced(ctx->params.data(), ctx->n_inst, cols, balance * ctx->ncu)
-                         : plan_uniform(ctx->params.data(), ctx->n_inst, rows, cols);
+    const int frw = full_rows ? fullrow_waves(ctx->params.data(), ctx->n_inst) : 0;
+    if (full_rows && !frw)
+        return fail(ctx, LBM_EUNSUPPORTED, "full rows need every lattice width a multiple of 64, at most 512");
+    StripPlan plan = full_rows    ? plan_fullrow(ctx->params.data(), ctx->n_inst, rows, frw)
+                     : balance > 0 ? plan_balanced(ctx->params.data(), ctx->n_inst, cols, balance * ctx->ncu)
+                                   : plan_uniform(ctx->params.data(), ctx->n_inst, rows, cols);
     if ((int)plan.segs.size() > ctx->layout.max_strips)
         return fail(ctx, LBM_EINVAL, "strip table overflow");
-    if (!plan_fits(plan, strip_waves(cols))) return fail(ctx, LBM_EINVAL, "strip wider than its workgroup");
+    if (!full_rows && !plan_fits(plan, strip_waves(cols)))
+        return fail(ctx, LBM_EINVAL, "strip wider than its workgroup");
     // the tables are read by kernels already queued: order the copies after them
     HIP_TRY(ctx, hipMemcpyAsync(ctx->dev.strips, plan.segs.data(), sizeof(int4) * plan.segs.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
@@ -800,10 +880,12 @@ static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->dev.nstrips = (int)plan.segs.size();
     ctx->dev.nwg = (int)plan.first.size() - 1;
-    ctx->dev.nw = strip_waves(cols);
+    ctx->dev.nw = full_rows ? frw : strip_waves(cols);
+    ctx->dev.fr = full_rows ? 1 : 0;
     ctx->chunk = rows;
     ctx->width = cols;
-    ctx->balance = balance;
+    ctx->balance = full_rows ? 0 : balance;
+    ctx->full_rows = full_rows;
     for (int i = 0; i < 2; ++i)
         if (ctx->graph[i]) {
             (void)hipGraphExecDestroy(ctx->graph[i]);
@@ -817,8 +899,17 @@ int lbm_set_tiling(lbm_ctx *ctx, int32_t chunk_rows)
     CTX_CHECK(ctx);
     if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
         return fail(ctx, LBM_EINVAL, "chunk_rows must be in [2, 65535]");
-    return set_strips(ctx, chunk_rows, ctx->width, 0);
+    return set_strips(ctx, chunk_rows, ctx->width, 0, ctx->full_rows);
 }
+
+int lbm_set_full_rows(lbm_ctx *ctx, int32_t on)
+{
+    CTX_CHECK(ctx);
+    if (on != 0 && on != 1) return fail(ctx, LBM_EINVAL, "on must be 0 or 1");
+    return set_strips(ctx, ctx->chunk, ctx->width, 0, on);
+}
+
+int32_t lbm_get_full_rows(const lbm_ctx *ctx) { return ctx ? ctx->full_rows : -1; }
 
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
 {
@@ -843,7 +934,7 @@ int32_t lbm_get_balance(const lbm_ctx *ctx) { return ctx ? ctx->balance : -1; }
 int32_t lbm_get_workgroups(const lbm_ctx *ctx) { return ctx ? ctx->dev.nwg : -1; }
 
 int lbm_plan_workgroups(const lbm_params *params, int32_t n_inst, int32_t cols, int32_t chunk_rows,
-                        int32_t wgs, int32_t *nwg, int32_t *nsegs)
+                        int32_t wgs, int32_t full_rows, int32_t *nwg, int32_t *nsegs)
 {
     if (!params || !nwg || n_inst < 1) return fail(nullptr, LBM_EINVAL, "null argument or n_inst < 1");
     for (int i = 0; i < n_inst; ++i) {
@@ -855,9 +946,18 @@ int lbm_plan_workgroups(const lbm_params *params, int32_t n_inst, int32_t cols, 
     if (wgs < 0 || wgs > MAX_WG) return fail(nullptr, LBM_EINVAL, "wgs must be in [0, 8192]");
     if (wgs == 0 && (chunk_rows < MIN_CHUNK || chunk_rows > 65535))
         return fail(nullptr, LBM_EINVAL, "chunk_rows must be in [2, 65535]");
-    StripPlan plan = wgs > 0 ? plan_balanced(params, n_inst, cols, wgs)
-                             : plan_uniform(params, n_inst, chunk_rows, cols);
-    if (!plan_fits(plan, strip_waves(cols))) return fail(nullptr, LBM_EINVAL, "strip wider than its workgroup");
+    if (full_rows) {
+        if (!fullrow_waves(params, n_inst))
+            return fail(nullptr, LBM_EUNSUPPORTED,
+                        "full rows need every lattice width a multiple of 64, at most 512");
+        if (chunk_rows < MIN_CHUNK || chunk_rows > 65535)
+            return fail(nullptr, LBM_EINVAL, "chunk_rows must be in [2, 65535]");
+    }
+    StripPlan plan = full_rows ? plan_fullrow(params, n_inst, chunk_rows, fullrow_waves(params, n_inst))
+                     : wgs > 0 ? plan_balanced(params, n_inst, cols, wgs)
+                               : plan_uniform(params, n_inst, chunk_rows, cols);
+    if (!full_rows && !plan_fits(plan, strip_waves(cols)))
+        return fail(nullptr, LBM_EINVAL, "strip wider than its workgroup");
     if ((int)plan.segs.size() > max_strips(params, n_inst))
         return fail(nullptr, LBM_EINVAL, "strip table overflow");
     *nwg = (int32_t)plan.first.size() - 1;

@@ -29,6 +29,7 @@ struct Dev {
     int nw;         // wavefronts per strip of the fused step (1, 2, 4 or 8)
     int nwg;        // workgroups of the fused step
     int forcing;    // 0: Guo term (Eq. 5), 1: velocity shift of the original model
+    int fr;         // 1: full-row segments {inst, w0, Y0, k | ho << 16} (nx = 64 k)
 };
 
 // wavefronts per strip for a strip of `cols` output columns

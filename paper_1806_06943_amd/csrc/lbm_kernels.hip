@@ -118,10 +118,13 @@ __device__ __forceinline__ float from_right(float v)
 
 // Density ring of a strip of NW wavefronts: RR rows (a rolling window over
 // lattice rows) of 64 NW columns (plus 4 that no stencil of a used lane
-// reads), column j holding lattice column X0 - 1 - HALO + j.
-template <int NW>
+// reads), column j holding lattice column X0 - 1 - HALO + j.  In full-row
+// mode (FR) the group of wavefronts that starts at wavefront w0 owns the
+// 68 w0 ... columns: lattice column X at 68 w0 + HALO + X, with the HALO
+// columns on either side holding the periodic wrap of the row.
+template <int NW, int FR>
 struct RingW {
-    static constexpr int W = 64 * NW + 2 * HALO;
+    static constexpr int W = FR ? 68 * NW : 64 * NW + 2 * HALO;
     float rho[2][RR][W];
     float psi[2][RR][W];
     float dev[2][RR][W];  // density deviations (own-node term of the collision)
@@ -175,26 +178,62 @@ struct RingAccW {
 // Register budget: two waves per SIMD (at most 256 VGPRs; the kernel uses
 // about 211), which every strip width meets without spilling although four
 // rows of populations are live across the collision.
-template <int NW, int FS>
+//
+// FR = 1 (full rows): for lattices whose width is a multiple of 64, a group
+// of k = nx / 64 wavefronts covers whole rows, lane l of the group's j-th
+// wavefront owning column 64 j + l: every lane loads, collides and writes
+// its own column, and no column is loaded or collided twice.  The ring holds
+// the row with its periodic wrap, and the x shift of the pull crosses from
+// the group's last wavefront to its first through the edge exchange.  A
+// workgroup then advances several groups at once (the segments of its
+// table entry range, each {inst, w0, Y0, k | ho << 16}, all with the same
+// ho); wavefronts that no group uses only keep the workgroup's barriers.
+template <int NW, int FS, int FR>
 __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     const KInst *__restrict__ insts, const int4 *__restrict__ segs, const int *__restrict__ first,
     int par, StepOvr ovr)
 {
-    __shared__ RingW<NW> R;
+    __shared__ RingW<NW, FR> R;
     // edge values of each wavefront for its neighbours: [wave][side][6]
     __shared__ float edge[NW][2][6];
+    const int L = (int)threadIdx.x;
+    const int l = L & 63;
+    // the wavefront index, as a scalar (it is uniform within a wavefront)
+    const int wv = __builtin_amdgcn_readfirstlane(L >> 6);
     // the workgroup's segments, one after the other (a segment ends with a
-    // barrier after which no thread reads the ring or the edges again)
-    const int sg_end = first[blockIdx.x + 1];
-    for (int sg = first[blockIdx.x]; sg < sg_end; ++sg) {
+    // barrier after which no thread reads the ring or the edges again); in
+    // full-row mode one pass over concurrent groups
+    const int sg_begin = first[blockIdx.x], sg_end = first[blockIdx.x + 1];
+    const int npass = FR ? 1 : sg_end - sg_begin;
+    for (int pass = 0; pass < npass; ++pass) {
+    int sg = sg_begin + pass;
+    int w0 = 0, gk = 0;  // full-row group: first wavefront and wavefront count
+    if constexpr (FR) {
+        int mine = -1;
+        for (int e = sg_begin; e < sg_end; ++e) {
+            const int4 te = segs[e];
+            const int k = te.w & 0xffff;
+            if (wv >= te.y && wv < te.y + k) {
+                mine = e;
+                w0 = te.y;
+                gk = k;
+            }
+        }
+        if (mine < 0) {
+            // no group here: keep the barriers of the others (one after the
+            // ring fill, two per row of the common height)
+            const int nitw = (int)((uint32_t)segs[sg_begin].w >> 16) + 2;
+            for (int b = 0; b < 1 + 2 * nitw; ++b) __syncthreads();
+            continue;
+        }
+        sg = mine;
+    }
     const int4 t = segs[sg];
     const KInst &G = insts[t.x];
     // arithmetic parameters copied once: the buffer stores below could
     // otherwise alias them
     const KPar P = kpar(G);
-    const int X0 = t.y, Y0 = t.z, wo = t.w & 0xffff, ho = (int)((uint32_t)t.w >> 16);
-    const int L = (int)threadIdx.x;
-    const int l = L & 63, wv = L >> 6;
+    const int X0 = FR ? 0 : t.y, Y0 = t.z, wo = t.w & 0xffff, ho = (int)((uint32_t)t.w >> 16);
     const int nx = G.nx, ny = G.ny, walls = G.walls;
     const uint32_t pb = (uint32_t)G.pitch;        // nodes per row (with padding)
     const uint32_t frowb = 72u * pb;              // bytes per population row
@@ -214,11 +253,19 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     // outer two are the one-column halo whose collision the neighbouring
     // strips also compute), lanes HALO + 1 .. wo + HALO write.  Lanes beyond
     // read zeros and write nothing.
+    // In full-row mode lane l of the group's wavefront wv - w0 owns column
+    // X = 64 (wv - w0) + l < nx, loads, collides and writes it; its ring
+    // column is 68 w0 + HALO + X, and the lanes of the first and last HALO
+    // columns also fill the wrap columns at the other end of the row.
     const int jmax = wo + 1 + 2 * HALO;
-    const bool outl = (L >= HALO + 1) && (L <= wo + HALO);
-    const uint32_t xl = (uint32_t)wrapi(X0 - 1 - HALO + L, nx);
-    const bool needf = L <= jmax;
+    const int X = FR ? 64 * (wv - w0) + l : X0 - 1 - HALO + L;
+    const bool outl = FR ? true : (L >= HALO + 1) && (L <= wo + HALO);
+    const uint32_t xl = FR ? (uint32_t)X : (uint32_t)wrapi(X, nx);
+    const bool needf = FR ? true : L <= jmax;
     const uint32_t xf16 = needf ? xl * 16u : DROP, xf8 = needf ? xl * 8u : DROP;
+    const int rbase = 68 * w0 + HALO;
+    const int cl = FR ? rbase + X : L;  // this lane's ring column
+    const int cw = !FR ? -1 : X >= nx - HALO ? rbase + X - nx : X < HALO ? rbase + nx + X : -1;
 
     // lattice row r -> wrapped row index, or -1 beyond a wall (general
     // form, used once per cursor); cursors then advance by one row
@@ -269,12 +316,20 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         const float da = sum9(q[0]), db = sum9(q[1]);
         const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
         const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + db;
-        R.rho[0][slot][L] = ra;
-        R.rho[1][slot][L] = rb;
-        R.psi[0][slot][L] = wall ? P.psi_wall[0] : psi_of(P, ra);
-        R.psi[1][slot][L] = wall ? P.psi_wall[1] : psi_of(P, rb);
-        R.dev[0][slot][L] = da;
-        R.dev[1][slot][L] = db;
+        const float pa = wall ? P.psi_wall[0] : psi_of(P, ra);
+        const float pbv = wall ? P.psi_wall[1] : psi_of(P, rb);
+        R.rho[0][slot][cl] = ra;
+        R.rho[1][slot][cl] = rb;
+        R.psi[0][slot][cl] = pa;
+        R.psi[1][slot][cl] = pbv;
+        R.dev[0][slot][cl] = da;
+        R.dev[1][slot][cl] = db;
+        if (FR && cw >= 0) {  // the row's periodic wrap (stencil values only)
+            R.rho[0][slot][cw] = ra;
+            R.rho[1][slot][cw] = rb;
+            R.psi[0][slot][cw] = pa;
+            R.psi[1][slot][cw] = pbv;
+        }
     };
 
     // ring rows Y0 - 3 .. Y0 + 1 into slots 0..4 (slot[d] is the slot of row
@@ -332,12 +387,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         // and never used)
         {
             float F[2][2];
-            stencil_force(P, RingAccW<RingW<NW>>{R, slot, L}, F);
+            stencil_force(P, RingAccW<RingW<NW, FR>>{R, slot, cl}, F);
             float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                drho[k] = R.dev[k][slot[HALO]][L];
-                rho[k] = R.rho[k][slot[HALO]][L];
+                drho[k] = R.dev[k][slot[HALO]][cl];
+                rho[k] = R.rho[k][slot[HALO]][cl];
                 float mx, my;
                 mom9(fa[k], mx, my);
                 jx[k] = FS ? mx : fmaf(0.5f, F[k][0], mx);
@@ -362,7 +417,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         // publishes the right-moving ones (1, 5, 8) for the next wavefront's
         // lane 0, lane 0 the left-moving ones (3, 6, 7) for the previous
         // wavefront's lane 63
-        if constexpr (NW > 1) {
+        if constexpr (NW > 1 || FR) {
             if (l == 63) {
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
@@ -383,9 +438,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         // every collision of row c is done: the ring row of c - 2 is free and
         // the edge values are visible
         __syncthreads();
-        const int wl = wv > 0 ? wv - 1 : 0, wr = wv < NW - 1 ? wv + 1 : NW - 1;
-        const bool takel = NW > 1 && l == 0 && wv > 0;
-        const bool taker = NW > 1 && l == 63 && wv < NW - 1;
+        // neighbouring wavefronts of the x shift: inside the strip, or, in
+        // full-row mode, around the group's row (its last wavefront's right
+        // neighbour is its first)
+        const int wl = FR ? (wv == w0 ? w0 + gk - 1 : wv - 1) : (wv > 0 ? wv - 1 : 0);
+        const int wr = FR ? (wv == w0 + gk - 1 ? w0 : wv + 1) : (wv < NW - 1 ? wv + 1 : NW - 1);
+        const bool takel = FR ? l == 0 : NW > 1 && l == 0 && wv > 0;
+        const bool taker = FR ? l == 63 : NW > 1 && l == 63 && wv < NW - 1;
 
         // stream into output row o = c - 1; the first two iterations have no
         // output row yet and write nothing
@@ -394,7 +453,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
             const bool wlo = walls && o == 0;
             const bool whi = walls && o == ny - 1;
             const bool st = outl && it >= 2;
-            const uint32_t xo = (uint32_t)(X0 - 1 - HALO + L);
+            const uint32_t xo = (uint32_t)X;
             const uint32_t off4 = st ? (uint32_t)o * frowb + xo * 16u : DROP;
             const uint32_t off2 = st ? (uint32_t)o * frowb + xo * 8u : DROP;
             const uint32_t roff = st && ovr.wrho ? (uint32_t)o * rrowb + xo * 8u : DROP;
@@ -406,7 +465,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
                 float g[9];
                 float l1 = from_left(Sprev[k][1]), l5 = from_left(Uprev[k][1]), l8 = from_left(S[k][8]);
                 float r3 = from_right(Sprev[k][3]), r6 = from_right(Uprev[k][2]), r7 = from_right(S[k][7]);
-                if constexpr (NW > 1) {
+                if constexpr (NW > 1 || FR) {
                     l1 = takel ? edge[wl][1][3 * k + 0] : l1;
                     l5 = takel ? edge[wl][1][3 * k + 1] : l5;
                     l8 = takel ? edge[wl][1][3 * k + 2] : l8;
@@ -907,27 +966,24 @@ hipError_t launch_density(const Dev &d, int par, hipStream_t st)
     return hipSuccess;
 }
 
+template <int FS, int FR>
+static hipError_t launch_fused(const Dev &d, int par, const StepOvr &o, hipStream_t st)
+{
+    switch (d.nw) {
+    case 1: k_fused_step<1, FS, FR><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+    case 2: k_fused_step<2, FS, FR><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+    case 4: k_fused_step<4, FS, FR><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+    case 8: k_fused_step<8, FS, FR><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t st)
 {
-    if (d.forcing) {
-        switch (d.nw) {
-        case 1: k_fused_step<1, 1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 2: k_fused_step<2, 1><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 4: k_fused_step<4, 1><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 8: k_fused_step<8, 1><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (d.nw) {
-        case 1: k_fused_step<1, 0><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 2: k_fused_step<2, 0><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 4: k_fused_step<4, 0><<<d.nwg, 256, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        case 8: k_fused_step<8, 0><<<d.nwg, 512, 0, st>>>(d.insts, d.strips, d.first, par, o); break;
-        default: return hipErrorInvalidValue;
-        }
-    }
-    LAUNCH_CHECK();
-    return hipSuccess;
+    if (d.forcing)
+        return d.fr ? launch_fused<1, 1>(d, par, o, st) : launch_fused<1, 0>(d, par, o, st);
+    return d.fr ? launch_fused<0, 1>(d, par, o, st) : launch_fused<0, 0>(d, par, o, st);
 }
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)

@@ -108,8 +108,11 @@ def lib() -> ctypes.CDLL:
         L.lbm_get_balance.argtypes = [vp]
         L.lbm_get_balance.restype = ctypes.c_int32
         L.lbm_plan_workgroups.argtypes = [P(lbm_params), ctypes.c_int32, ctypes.c_int32,
-                                          ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
-                                          P(ctypes.c_int32)]
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          P(ctypes.c_int32), P(ctypes.c_int32)]
+        L.lbm_set_full_rows.argtypes = [vp, ctypes.c_int32]
+        L.lbm_get_full_rows.argtypes = [vp]
+        L.lbm_get_full_rows.restype = ctypes.c_int32
         L.lbm_get_workgroups.argtypes = [vp]
         L.lbm_get_workgroups.restype = ctypes.c_int32
         L.lbm_get_strip_width.argtypes = [vp]
@@ -272,13 +275,22 @@ def lbm_get_balance(ctx) -> int:
     return int(lib().lbm_get_balance(ctx))
 
 
-def lbm_plan_workgroups(params, cols: int, chunk_rows: int = 16, wgs: int = 0):
+def lbm_plan_workgroups(params, cols: int, chunk_rows: int = 16, wgs: int = 0,
+                        full_rows: int = 0):
     """(workgroups, segments) of a strip plan, planned on the host."""
     arr = (lbm_params * len(params))(*params)
     nwg, nseg = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().lbm_plan_workgroups(arr, len(params), int(cols), int(chunk_rows), int(wgs),
-                                     ctypes.byref(nwg), ctypes.byref(nseg)))
+                                     int(full_rows), ctypes.byref(nwg), ctypes.byref(nseg)))
     return int(nwg.value), int(nseg.value)
+
+
+def lbm_set_full_rows(ctx, on: int):
+    _check(lib().lbm_set_full_rows(ctx, int(on)), ctx)
+
+
+def lbm_get_full_rows(ctx) -> int:
+    return int(lib().lbm_get_full_rows(ctx))
 
 
 def lbm_get_workgroups(ctx) -> int:

@@ -10,10 +10,12 @@ balanced (64 n - 2 columns) or placed at multiples of a multiple of 16
 columns (output rows start on 64-byte boundaries); for each width the
 uniform plans (chunks of a candidate height) and the balanced plans (1 to 4
 workgroups per compute unit, equal shares of rows) are timed.  Beside a fixed
-list of heights, each width gets the heights fitted to the GPU: for k = 1..4
+list of heights, each width gets the heights fitted to the GPU: for k = 1..8
 the smallest height whose launch has at most k workgroups per compute unit
 (a launch just past such a multiple leaves most compute units idle for its
-last round of workgroups).
+last round of workgroups).  Contexts whose lattice widths are all multiples
+of 64 (at most 512) also time the full-row plans (lbm_set_full_rows) at the
+same heights.
 """
 from __future__ import annotations
 
@@ -34,7 +36,7 @@ CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), "
 
 def _key(sim, arch: str) -> str:
     shapes = sorted({(p.nx, p.ny) for p in sim.params})
-    return f"v3|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
+    return f"v4|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
         (f"|+{len(shapes) - 8}" if len(shapes) > 8 else "")
 
 
@@ -48,14 +50,28 @@ def _arch(sim) -> str:
 BALANCES = (1, 2, 3, 4)
 
 
-def apply(sim, width: int, height: int, balance: int = 0):
+def apply(sim, width: int, height: int, balance: int = 0, full_rows: int = 0):
     """Strip width, then either uniform chunks of `height` rows or, if balance > 0,
-    the balanced plan with `balance` workgroups per compute unit."""
+    the balanced plan with `balance` workgroups per compute unit; with
+    full_rows, the full-row plan of chunks of `height` rows (width unused)."""
+    if full_rows:
+        lbm.lbm_set_tiling(sim.ctx, int(height))
+        lbm.lbm_set_full_rows(sim.ctx, 1)
+        return
     lbm.lbm_set_strip_width(sim.ctx, int(width))
     if balance > 0:
         lbm.lbm_set_balance(sim.ctx, int(balance))
     else:
         lbm.lbm_set_tiling(sim.ctx, int(height))
+
+
+def full_rows_possible(sim) -> bool:
+    """Every lattice width a multiple of 64, at most 512 (lbm_set_full_rows)."""
+    try:
+        lbm.lbm_plan_workgroups(sim.params, 58, 16, 0, 1)
+        return True
+    except lbm.LBMError:
+        return False
 
 
 def _ncu(sim) -> int:
@@ -68,22 +84,25 @@ def _ncu(sim) -> int:
 FIT_KMAX = 8  # workgroups per CU up to which fitted heights are tried
 
 
-def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX) -> list:
+def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX, full_rows: int = 0) -> list:
     """For k = 1..kmax the smallest uniform strip height at which the launch has at
-    most k * ncu workgroups (the count falls as the height grows)."""
+    most k * ncu workgroups (the count falls as the height grows); planned on the
+    host (lbm_plan_workgroups)."""
     hmin = MIN_HEIGHT
     hmax = min(max(max(p.ny for p in sim.params), hmin), MAX_HEIGHT)
+
+    def count(h):
+        return lbm.lbm_plan_workgroups(sim.params, width, h, 0, full_rows)[0]
+
     out = set()
     for k in range(1, kmax + 1):
         target = k * ncu
-        apply(sim, width, hmax)
-        if lbm.lbm_get_workgroups(sim.ctx) > target:
+        if count(hmax) > target:
             continue
         lo, hi = hmin, hmax
         while lo < hi:
             mid = (lo + hi) // 2
-            apply(sim, width, mid)
-            if lbm.lbm_get_workgroups(sim.ctx) <= target:
+            if count(mid) <= target:
                 hi = mid
             else:
                 lo = mid + 1
@@ -103,9 +122,9 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
                 cache = json.load(fh)
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache and "balance" in cache[key]:
+    if use_cache and key in cache and "full_rows" in cache[key]:
         e = cache[key]
-        apply(sim, e["width"], e["best"], e["balance"])
+        apply(sim, e["width"], e["best"], e["balance"], e["full_rows"])
         return e
     times = {}
     ncu = _ncu(sim)
@@ -118,10 +137,17 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
             apply(sim, wdt, 0, b)
             lbm.lbm_profile_step(sim.ctx, 3)
             times[(wdt, 0, b)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+    if full_rows_possible(sim):  # width 0 marks a full-row plan
+        for h in sorted(set(candidates) | set(fitted_heights(sim, 58, ncu, full_rows=1))):
+            apply(sim, 0, h, 0, 1)
+            lbm.lbm_profile_step(sim.ctx, 3)
+            times[(0, h, 0)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
     bw, bh, bb = min(times, key=times.get)
-    apply(sim, bw, bh, bb)
-    entry = {"best": bh, "width": bw, "balance": bb,
-             "ms": {(f"{w}x{h}" if b == 0 else f"{w}xbal{b}"): v for (w, h, b), v in times.items()}}
+    fr = 1 if bw == 0 else 0
+    apply(sim, bw, bh, bb, fr)
+    entry = {"best": bh, "width": bw, "balance": bb, "full_rows": fr,
+             "ms": {(f"fr{h}" if w == 0 else f"{w}x{h}" if b == 0 else f"{w}xbal{b}"): v
+                    for (w, h, b), v in times.items()}}
     if use_cache:
         cache[key] = entry
         try:

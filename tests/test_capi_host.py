@@ -110,7 +110,7 @@ def test_host_planner_counts(seed):
             assert n == nseg == want, (cols, H)
         strip_rows = sum(p.ny * _ceil(p.nx, cols) for p in ps)
         for G in (1, 7, 256, 1024, 8192):
-            n, nseg = lbm.lbm_plan_workgroups(ps, cols, 0, G)
+            n, nseg = lbm.lbm_plan_workgroups(ps, cols, 2, G)
             assert n == min(G, strip_rows) and nseg >= n, (cols, G)
     with pytest.raises(lbm.LBMError):
         lbm.lbm_plan_workgroups(ps, 15, 16)
@@ -127,3 +127,32 @@ def test_host_planner_tall_chunks():
     for H in (32767, 32768, 40000, 65535):
         n, _ = lbm.lbm_plan_workgroups(p, 58, H)
         assert n == _ceil(466033, H) * 2
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_host_full_row_plans(seed):
+    """Full-row plans: one group of nx / 64 wavefronts per row chunk; groups of
+    equal height share workgroups of the smallest power-of-two wavefront count
+    that holds the widest lattice, so at least ceil(total wavefronts / NW)
+    workgroups and at most one per group."""
+    r = np.random.default_rng(40 + seed)
+    ps = [_ok_params(nx=64 * int(r.integers(1, 9)), ny=int(r.integers(1, 300)),
+                     walls=int(r.integers(0, 2))) for _ in range(int(r.integers(1, 12)))]
+    kmax = max(p.nx // 64 for p in ps)
+    NW = 1 if kmax <= 1 else 2 if kmax <= 2 else 4 if kmax <= 4 else 8
+    for H in (2, 3, 7, 16, 64, 65535):
+        n, nseg = lbm.lbm_plan_workgroups(ps, 58, H, 0, 1)
+        groups = sum(_ceil(p.ny, H) for p in ps)
+        waves = sum(_ceil(p.ny, H) * (p.nx // 64) for p in ps)
+        assert nseg == groups
+        assert _ceil(waves, NW) <= n <= groups
+
+
+def test_host_full_rows_refuse_other_widths():
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_plan_workgroups([_ok_params(nx=96, ny=8)], 58, 16, 0, 1)
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_plan_workgroups([_ok_params(nx=576, ny=8)], 58, 16, 0, 1)
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    lbm.lbm_plan_workgroups([_ok_params(nx=512, ny=8), _ok_params(nx=64, ny=3)], 58, 16, 0, 1)

@@ -461,6 +461,114 @@ def test_strip_heights_past_15_bits(torch):
         assert np.array_equal(f, ref), h
 
 
+FULL_ROW_CASES = {
+    "64x40": [(64, 40, 0)],
+    "128x33w": [(128, 33, 1)],
+    "192x50": [(192, 50, 0)],
+    "256x24w": [(256, 24, 1)],
+    "320x17": [(320, 17, 0)],
+    "512x9w": [(512, 9, 1)],
+    "64x1": [(64, 1, 0)],
+    "mixed": [(64, 64, 0), (128, 40, 1), (192, 30, 0), (256, 20, 1), (64, 7, 1)],
+}
+
+
+def full_row_instances(spec, forcing=0):
+    out = []
+    for j, (nx, ny, walls) in enumerate(spec):
+        r = np.random.default_rng(1000 + 17 * j + nx + ny)
+        yy, xx = np.mgrid[0:ny, 0:nx]
+        disc = (xx - nx / 3) ** 2 + (yy - ny / 2) ** 2 <= (min(nx, ny) / 3) ** 2
+        rA = np.where(disc, 1.0, 0.03) + r.uniform(-1e-3, 1e-3, (ny, nx))
+        rB = np.where(disc, 0.03, 1.0) + r.uniform(-1e-3, 1e-3, (ny, nx))
+        out.append(dict(nx=nx, ny=ny, rhoA=rA, rhoB=rB, G_AB=3.0, G1=-7.4, G2=6.4,
+                        tau=(1.0, 1.0) if forcing else (1.0, 0.7), walls=walls,
+                        rho_wall=(0.03, 1.0), g=((2e-5, 1e-6), (2e-5, 1e-6)), forcing=forcing))
+    return out
+
+
+@pytest.mark.parametrize("case", sorted(FULL_ROW_CASES))
+def test_full_row_plans_equal_strip_plans(torch, case):
+    """Full-row plans (groups of nx / 64 wavefronts covering whole rows, several
+    groups per workgroup) give the strip plans' results bit for bit: lattice
+    widths 64 to 512, walls, one-row tori, mixed widths in one context, chunk
+    heights from 2 rows to whole lattices; for the velocity shift too."""
+    say("full rows", case)
+    for forcing in (0, 1):
+        insts = full_row_instances(FULL_ROW_CASES[case], forcing)
+        ref = None
+        for h in (0, 2, 3, 5, 16, 65535):
+            sim = lbm.Sim(insts)
+            if h:
+                lbm.lbm_set_tiling(sim.ctx, h)
+                lbm.lbm_set_full_rows(sim.ctx, 1)
+                assert lbm.lbm_get_full_rows(sim.ctx) == 1
+            sim.step(21)
+            f = [sim.populations(i).cpu().numpy() for i in range(len(insts))]
+            sim.close()
+            if ref is None:
+                ref = f
+            for i in range(len(insts)):
+                assert np.array_equal(f[i], ref[i]), (case, forcing, h, i)
+
+
+def test_full_row_recording_equals_strip_recording(torch):
+    """A recorded window (the step's override buffers, densities written) under a
+    full-row plan stores the same states as under a strip plan, bit for bit."""
+    insts = full_row_instances([(128, 48, 1), (64, 30, 0)])
+    stores = []
+    for fr in (0, 1):
+        sim = lbm.Sim(insts)
+        if fr:
+            lbm.lbm_set_tiling(sim.ctx, 7)
+            lbm.lbm_set_full_rows(sim.ctx, 1)
+        sim.step(5)
+        n = lbm.lbm_record_floats(sim.ctx, 0)
+        S = torch.zeros((6, n), dtype=torch.float32, device="cuda:0")
+        lbm.lbm_record(sim.ctx, 0, 5, S.data_ptr())
+        torch.cuda.synchronize()
+        stores.append((S.cpu().numpy(), sim.populations(0).cpu().numpy(), sim.populations(1).cpu().numpy()))
+        sim.close()
+    # a slot: populations (18 ny pitch floats, padded by 64) then densities
+    # (2 ny pitch, padded by 64); the pads hold whatever the workspace held
+    nf, nr = 18 * 48 * 128, 2 * 48 * 128
+    for a, b in ((stores[0][0], stores[1][0]),):
+        assert a.shape[1] == nf + 64 + nr + 64
+        assert np.array_equal(a[:5, :nf], b[:5, :nf])
+        assert np.array_equal(a[:5, nf + 64:nf + 64 + nr], b[:5, nf + 64:nf + 64 + nr])
+    for j in (1, 2):
+        assert np.array_equal(stores[0][j], stores[1][j])
+
+
+def test_full_rows_refused_for_other_widths(torch):
+    w = W.droplet(nx=96, ny=64)
+    sim = lbm.Sim([lbm.workload_instance(w)])
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_set_full_rows(sim.ctx, 1)
+    assert ei.value.code == lbm.LBM_EUNSUPPORTED
+    assert lbm.lbm_get_full_rows(sim.ctx) == 0
+    sim.close()
+
+
+def test_batched_workload_full_rows_equal_strips(torch):
+    """The 96-instance droplet batch under its strip plan and under full-row plans."""
+    ws = W.batched()
+    insts = [lbm.workload_instance(w) for w in ws]
+    ref = None
+    for fr, h in ((0, 64), (1, 64), (1, 21)):
+        sim = lbm.Sim(insts)
+        lbm.lbm_set_tiling(sim.ctx, h)
+        if fr:
+            lbm.lbm_set_full_rows(sim.ctx, 1)
+        sim.step(40)
+        f = [sim.populations(i).cpu().numpy() for i in (0, 1, 2, 5, 50, 95)]
+        sim.close()
+        if ref is None:
+            ref = f
+        for a, b in zip(f, ref):
+            assert np.array_equal(a, b), (fr, h)
+
+
 @pytest.mark.parametrize("nx,ny,walls", [(200, 96, 1), (600, 40, 0), (37, 21, 1)])
 def test_strip_width_does_not_change_results(torch, nx, ny, walls):
     """Strips of 1 to 8 wavefronts, balanced or 64-byte aligned, uniform chunks or an

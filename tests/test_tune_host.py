@@ -1,6 +1,6 @@
 """Host logic of the strip-plan tuner: the fitted-height search, with the
-library's workgroup count replaced by the count of a uniform plan (strips x
-chunks), so it runs without a GPU."""
+library's host planner replaced by the count of a uniform plan (strips x
+chunks), so the search itself is checked against a brute force."""
 import types
 
 import pytest
@@ -16,20 +16,17 @@ class FakeSim:
 
 
 def install(monkeypatch, sim, strips):
-    """apply() records the plan; lbm_get_workgroups() returns strips * ceil(ny / h)."""
+    """lbm_plan_workgroups() records the height and returns strips * ceil(ny / h)."""
     applied = []
 
-    def apply(s, width, height, balance=0):
-        assert height >= tune.MIN_HEIGHT, height  # the library rejects smaller heights
-        s.plan = (width, height)
+    def plan(params, width, height, wgs=0, full_rows=0):
+        assert tune.MIN_HEIGHT <= height <= tune.MAX_HEIGHT, height  # the library's range
         applied.append(height)
+        ny = params[0].ny
+        n = strips * -(-ny // height)
+        return n, n
 
-    def workgroups(ctx):
-        ny = sim.params[0].ny
-        return strips * -(-ny // sim.plan[1])
-
-    monkeypatch.setattr(tune, "apply", apply)
-    monkeypatch.setattr(tune.lbm, "lbm_get_workgroups", workgroups)
+    monkeypatch.setattr(tune.lbm, "lbm_plan_workgroups", plan)
     return applied
 
 
@@ -57,3 +54,15 @@ def test_no_height_below_the_library_minimum_is_tried(monkeypatch):
     applied = install(monkeypatch, sim, 34)
     hs = tune.fitted_heights(sim, 58, 256)
     assert min(applied) >= tune.MIN_HEIGHT and all(h >= tune.MIN_HEIGHT for h in hs)
+
+
+def test_fitted_heights_of_a_real_plan_stay_in_range():
+    """With the library's own host planner: the accepted 64 x 466033 lattice (more
+    rows than one chunk may hold) gets heights within the range of lbm_set_tiling."""
+    from paper_1806_06943_amd import lbm
+    p = lbm.make_params(nx=64, ny=466033, G_AB=3.0, G1=-7.4, G2=6.4, tau=(1.0, 0.6), walls=1)
+    sim = FakeSim(64, 466033)
+    sim.params = [p]
+    for fr in (0, 1):
+        hs = tune.fitted_heights(sim, 58, 256, full_rows=fr)
+        assert hs and all(tune.MIN_HEIGHT <= h <= tune.MAX_HEIGHT for h in hs)
