@@ -38,22 +38,44 @@ def main():
     ap.add_argument("--width", type=int, default=0, help="strip width (0: tune)")
     ap.add_argument("--chunk", type=int, default=16, help="strip height with --width")
     ap.add_argument("--balance", type=int, default=0, help="workgroups per CU with --width")
+    ap.add_argument("--full-rows", action="store_true",
+                    help="full-row plan of --chunk rows (lattice widths multiples of 64)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also launch the library's copy kernel over this many bytes "
+                         "(--launches times): the calibration of traffic counters")
     ap.add_argument("--launches", type=int, default=50)
     a = ap.parse_args()
     ws, sim = build(a.workload)
-    if a.width > 0:
+    if a.full_rows:
+        tune.apply(sim, 0, a.chunk, 0, 1)
+    elif a.width > 0:
         tune.apply(sim, a.width, a.chunk, a.balance)
     else:
         t = tune.tune(sim, use_cache=False)
-        print(f"tuned: width {t['width']} height {t['best']} balance {t['balance']}", flush=True)
+        print(f"tuned: width {t['width']} height {t['best']} balance {t['balance']} "
+              f"full rows {t['full_rows']}", flush=True)
     sim.step(20)
     ms = dict(lbm.lbm_profile_step(sim.ctx, a.launches))["k_fused_step"]
     nodes = sum(w.nx * w.ny for w in ws)
     print(f"{a.workload}: {len(ws)} instances, {nodes} nodes, plan {lbm.lbm_get_strip_width(sim.ctx)} x "
-          f"{lbm.lbm_get_tiling(sim.ctx)} balance {lbm.lbm_get_balance(sim.ctx)}, "
+          f"{lbm.lbm_get_tiling(sim.ctx)} balance {lbm.lbm_get_balance(sim.ctx)} "
+          f"full rows {lbm.lbm_get_full_rows(sim.ctx)}, "
           f"{lbm.lbm_get_workgroups(sim.ctx)} workgroups: {ms:.5f} ms per launch, "
           f"{nodes / (ms * 1e-3) / 1e6:.1f} MLUPS, {160.0 * nodes / (ms * 1e-3) / 1e9:.1f} GB/s at "
           f"160 B per lattice update", flush=True)
+    if a.copy_bytes > 0:
+        t = sim.torch
+        src = t.ones(a.copy_bytes // 4, dtype=t.float32, device=sim.device)
+        dst = t.empty_like(src)
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        for _ in range(a.launches):
+            lbm.lbm_copy_probe(sim.ctx, dst.data_ptr(), src.data_ptr(), a.copy_bytes)
+        e1.record(sim.stream)
+        t.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.launches
+        print(f"copy kernel: {a.copy_bytes} bytes, {ms:.5f} ms per launch, "
+              f"{2 * a.copy_bytes / (ms * 1e-3) / 1e9:.1f} GB/s moved", flush=True)
     sim.close()
 
 
