@@ -341,6 +341,14 @@ int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const fl
                         float *lam_out_dev, double *grad_dev, int32_t nrep, int32_t max_k,
                         double *ms, const char **names, int32_t *n_kernels);
 
+/* Debugging: in the checked build of the library (compiled with
+ * LBM_CHECK_LDS), every launch of the fused step checks the indices of its
+ * LDS ring and edge arrays, and *violations receives the number of
+ * out-of-range indices seen on this device since the previous call (the
+ * counter is then reset; an out-of-range index is counted, not used).
+ * Synchronises the stream.  LBM_EUNSUPPORTED in the plain build. */
+int lbm_lds_checks(lbm_ctx *ctx, int64_t *violations);
+
 /* Release host resources of the context (graphs, metadata).  Synchronises
  * the stream; never frees caller memory. */
 int lbm_destroy(lbm_ctx *ctx);

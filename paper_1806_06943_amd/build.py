@@ -22,14 +22,22 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# the checked build: the fused step counts out-of-range LDS indices
+# (lbm_lds_checks); load it with LBM_HIP_SO
+CHECKED = os.path.join(PKG, "liblbm_hip_check.so")
+
+
+def build(verbose: bool = False, checked: bool = True) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = TARGET + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, TARGET)
+    for target, extra in ((TARGET, []), (CHECKED, ["-DLBM_CHECK_LDS"])):
+        if extra and not checked:
+            continue
+        tmp = target + ".tmp"
+        cmd = [HIPCC] + FLAGS + extra + srcs + ["-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, target)
     return TARGET
 
 

@@ -1268,6 +1268,19 @@ int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const fl
     return rc;
 }
 
+int lbm_lds_checks(lbm_ctx *ctx, int64_t *violations)
+{
+    CTX_CHECK(ctx);
+    if (!violations) return fail(ctx, LBM_EINVAL, "null output");
+    unsigned int bad = 0;
+    hipError_t e = lds_checks(&bad, ctx->stream);
+    if (e == hipErrorNotSupported)
+        return fail(ctx, LBM_EUNSUPPORTED, "LDS index checks need the checked build (LBM_CHECK_LDS)");
+    if (e != hipSuccess) return hip_fail(ctx, e, "reading the LDS check counter");
+    *violations = (int64_t)bad;
+    return LBM_OK;
+}
+
 const char *lbm_last_error(const lbm_ctx *ctx)
 {
     return ctx ? ctx->err.c_str() : g_init_error.c_str();

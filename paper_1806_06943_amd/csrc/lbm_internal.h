@@ -62,6 +62,7 @@ hipError_t launch_observables(const Dev &d, int par, double margin, double *part
 // per-instance results res[ninst][NRES] as lbm_obs records out[ninst] (device)
 hipError_t launch_obs_pack(const Dev &d, const double *res, lbm_obs *out, hipStream_t st);
 hipError_t launch_copy(void *dst, const void *src, uint64_t nbytes, hipStream_t st);
+hipError_t lds_checks(unsigned int *bad, hipStream_t st);
 
 // ------------------------------------------------------------------ adjoint
 // Scratch planes of the instance's field region used by the adjoint passes:

@@ -130,6 +130,22 @@ struct RingW {
     float dev[2][RR][W];  // density deviations (own-node term of the collision)
 };
 
+// Index checks of the LDS ring and edge arrays, compiled in with
+// LBM_CHECK_LDS (the checked build of the library): an index outside its
+// array is counted in g_lds_bad (read back by lbm_lds_checks) instead of
+// being used; the plain build compiles them out.
+#ifdef LBM_CHECK_LDS
+__device__ unsigned int g_lds_bad;
+#define LDS_CHECK(ok)                                     \
+    do {                                                  \
+        if (!(ok)) atomicAdd(&g_lds_bad, 1u);              \
+    } while (0)
+#else
+#define LDS_CHECK(ok) \
+    do {              \
+    } while (0)
+#endif
+
 // accessor into the ring: slot[dy + 2] is the ring row of lattice row c + dy,
 // cx the ring column of the node
 template <class RT>
@@ -266,6 +282,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     const int rbase = 68 * w0 + HALO;
     const int cl = FR ? rbase + X : L;  // this lane's ring column
     const int cw = !FR ? -1 : X >= nx - HALO ? rbase + X - nx : X < HALO ? rbase + nx + X : -1;
+    // the stencil's centre column: the two load-only lanes at the left edge
+    // of a strip (their collision is never used) take lane 2's, so that no
+    // stencil reaches left of the ring
+    const int cs = FR ? cl : (cl < HALO ? HALO : cl);
+    [[maybe_unused]] constexpr int RW = RingW<NW, FR>::W;
+    LDS_CHECK(cl >= 0 && cl < RW && cs >= HALO && cs + HALO < RW);
+    LDS_CHECK(cw < RW);
+    LDS_CHECK(!FR || (w0 >= 0 && w0 + gk <= NW));
 
     // lattice row r -> wrapped row index, or -1 beyond a wall (general
     // form, used once per cursor); cursors then advance by one row
@@ -312,6 +336,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     // writes as rho(t + 1) (Eq. 6); a row beyond a wall takes the wall's
     // densities instead
     auto ring_store = [&](int slot, int ri, const float q[2][9]) {
+        LDS_CHECK(slot >= 0 && slot < RR);
         const bool wall = ri < 0;
         const float da = sum9(q[0]), db = sum9(q[1]);
         const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         // and never used)
         {
             float F[2][2];
-            stencil_force(P, RingAccW<RingW<NW, FR>>{R, slot, cl}, F);
+            stencil_force(P, RingAccW<RingW<NW, FR>>{R, slot, cs}, F);
             float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -445,6 +470,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         const int wr = FR ? (wv == w0 + gk - 1 ? w0 : wv + 1) : (wv < NW - 1 ? wv + 1 : NW - 1);
         const bool takel = FR ? l == 0 : NW > 1 && l == 0 && wv > 0;
         const bool taker = FR ? l == 63 : NW > 1 && l == 63 && wv < NW - 1;
+        LDS_CHECK(wl >= 0 && wl < NW && wr >= 0 && wr < NW && wv < NW);
 
         // stream into output row o = c - 1; the first two iterations have no
         // output row yet and write nothing
@@ -984,6 +1010,27 @@ hipError_t launch_step_ovr(const Dev &d, int par, const StepOvr &o, hipStream_t 
     if (d.forcing)
         return d.fr ? launch_fused<1, 1>(d, par, o, st) : launch_fused<1, 0>(d, par, o, st);
     return d.fr ? launch_fused<0, 1>(d, par, o, st) : launch_fused<0, 0>(d, par, o, st);
+}
+
+// count of out-of-range LDS indices the checked build has seen (and reset),
+// or hipErrorNotSupported in the plain build
+hipError_t lds_checks(unsigned int *bad, hipStream_t st)
+{
+#ifdef LBM_CHECK_LDS
+    hipError_t e = hipMemcpyFromSymbolAsync(bad, HIP_SYMBOL(g_lds_bad), sizeof(unsigned int), 0,
+                                            hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const unsigned int zero = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(g_lds_bad), &zero, sizeof zero, 0,
+                                   hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+#else
+    (void)bad;
+    (void)st;
+    return hipErrorNotSupported;
+#endif
 }
 
 hipError_t launch_step(const Dev &d, int par, hipStream_t st)

@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         L.lbm_profile_adjoint.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_char_p),
                                           P(ctypes.c_int32)]
+        L.lbm_lds_checks.argtypes = [vp, P(ctypes.c_int64)]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_last_error.argtypes = [vp]
         L.lbm_last_error.restype = ctypes.c_char_p
@@ -352,6 +353,13 @@ def lbm_profile_adjoint(ctx, inst: int, f_ptr: int, lam_in_ptr: int, lam_out_ptr
                                      int(nrep), max_k, ms, names, ctypes.byref(nk)), ctx)
     n = min(nk.value, max_k)
     return [(names[j].decode(), ms[j]) for j in range(n)]
+
+
+def lbm_lds_checks(ctx) -> int:
+    """Out-of-range LDS indices seen since the last call (checked build only)."""
+    n = ctypes.c_int64()
+    _check(lib().lbm_lds_checks(ctx, ctypes.byref(n)), ctx)
+    return int(n.value)
 
 
 def lbm_destroy(ctx):
