@@ -111,7 +111,9 @@ def parse():
     ap.add_argument("--emulsion-steps", type=int, default=50000,
                     help="0 skips the emulsion viscosity-ratio sweep")
     ap.add_argument("--adjoint-steps", type=int, default=4000, help="0 skips the adjoint form")
-    ap.add_argument("--adjoint-window", type=int, default=200)
+    ap.add_argument("--adjoint-window", type=int, default=0,
+                    help="steps per checkpoint window of the adjoint leg (0: the whole run "
+                         "when its states fit in device memory)")
     return ap.parse_args()
 
 
@@ -241,6 +243,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
     ms_fwd = timed(torch, fwd.stream, lambda: fwd.step(steps))
     fwd.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
+    window_used = prob.window
+    store_gb = prob.state_bytes() * min(window_used, steps) * (1 if window_used >= steps else 2) / 1e9
     for s in (prob.sim, prob.rec):  # forward context and window re-run context
         tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0),
                    tuning.get("full_rows", 0))
@@ -271,7 +275,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
     pf = N * steps / (ms_fwd * 1e-3) / 1e6
     return {"workload": f"{w.nx}x{w.ny} periodic, 16 droplets R=20, g_x=1e-6, "
                         "couplings (3.0, -7.4, 6.4), tau (1.0, 0.6)",
-            "steps": steps, "window": window, "objective": "J_dp (smooth pressure jump)",
+            "steps": steps, "window": window_used, "store_gb": round(store_gb, 2),
+            "objective": "J_dp (smooth pressure jump)",
             "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance", "full_rows")},
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),

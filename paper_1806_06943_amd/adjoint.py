@@ -13,7 +13,9 @@ The re-run of the window before runs meanwhile, in a second library context
 on a second stream fed by a second host thread, into the other of two state
 stores (events order each store's reuse), so the two latency-bound passes
 overlap.
-Memory: one state per window boundary plus two windows of states.
+Memory: one state per window boundary plus two windows of states; a run
+that is one window (window 0 picks that when every state of the run fits in
+the device memory) needs one store and re-runs nothing.
 
 Argument marshalling and bookkeeping only: the step, the adjoint step and the
 objective seeds all run in the HIP library.
@@ -36,9 +38,9 @@ class Problem:
     """
 
     def __init__(self, instance: dict, steps: int, objective: str, window: int = 200,
-                 device: str = "cuda:0"):
-        if steps < 0 or window < 1:
-            raise ValueError("steps must be >= 0 and window >= 1")
+                 device: str = "cuda:0", memory_fraction: float = 0.7):
+        if steps < 0 or window < 0:
+            raise ValueError("steps must be >= 0 and window >= 0 (0: chosen by memory)")
         self.sim = lbm.Sim([instance], device=device)
         self.torch = self.sim.torch
         # the context that re-runs windows, on a stream of its own (default
@@ -46,7 +48,6 @@ class Problem:
         self.rec = lbm.Sim([instance], device=device,
                            stream=self.torch.cuda.Stream(device=self.sim.device))
         self.steps = int(steps)
-        self.window = int(window)
         self.objective = objective
         self.f0 = self.sim.populations(0).clone()
         p = self.sim.params[0]
@@ -55,6 +56,26 @@ class Problem:
         self._store = None
         self._forwards = 0
         self._last_intact = False
+        self.window = int(window) if window > 0 else self.auto_window(memory_fraction)
+
+    def state_bytes(self) -> int:
+        """Bytes of one recorded state (populations and densities)."""
+        return 4 * int(lbm.lbm_record_floats(self.rec.ctx, 0))
+
+    def auto_window(self, fraction: float = 0.7) -> int:
+        """The whole run as one window when all its states fit in `fraction` of
+        the free device memory (one store, no window re-run), else the largest
+        window whose two stores fit."""
+        per = self.state_bytes()
+        t = self.torch
+        free, _ = t.cuda.mem_get_info(self.sim.device)
+        # memory the caching allocator holds but does not use is free for the store too
+        free += t.cuda.memory_reserved(self.sim.device) - t.cuda.memory_allocated(self.sim.device)
+        budget = fraction * free
+        n = max(self.steps, 1)
+        if n * per <= budget:
+            return n
+        return max(1, min(n, int(budget // (2 * per))))
 
     def theta(self) -> np.ndarray:
         return self.sim.theta(0)
@@ -68,12 +89,14 @@ class Problem:
         return out
 
     def _stores(self):
-        """The two window stores of states (allocated once, for windows of up to
-        `window` steps)."""
+        """The window stores of states, two (one for a run that is one window),
+        allocated once for windows of up to `window` steps."""
         m = min(self.window, max(self.steps, 1))
-        if self._store is None or self._store.shape[1] < m:
+        ns = 1 if len(self._windows()) <= 1 else 2
+        if self._store is None or self._store.shape[0] < ns or self._store.shape[1] < m:
             t = self.torch
-            self._store = t.empty((2, m, lbm.lbm_record_floats(self.rec.ctx, 0)), dtype=t.float32,
+            self._store = None
+            self._store = t.empty((ns, m, lbm.lbm_record_floats(self.rec.ctx, 0)), dtype=t.float32,
                                   device=self.sim.device)
         return self._store
 
@@ -187,6 +210,7 @@ class Problem:
         return J, g, lam0
 
     def close(self):
+        self._store = None
         self.rec.close()
         self.sim.close()
 

@@ -246,6 +246,27 @@ def test_backward_keeps_to_its_own_forward_pass(torch):
         prob.close()
 
 
+def test_window_chosen_by_memory(torch):
+    """window 0: a run whose states fit in device memory is one window, one
+    store, nothing re-run; J and lambda(0) equal the windowed run's bitwise,
+    the gradient up to the order of the FP64 per-window sums."""
+    say("window by memory")
+    d = droplet_instance(48, 48, 0, R=12, g=1e-5)
+    a = AD.Problem(d, steps=90, objective="dp", window=0)
+    assert a.window == 90
+    assert a.auto_window(fraction=1e-12) == 1
+    J0, g0, l0 = a.value_and_grad()
+    assert a._store.shape[0] == 1
+    J1, g1, l1 = a.value_and_grad()  # the recorded run again: bitwise the same
+    assert J1 == J0 and np.array_equal(g1, g0) and torch.equal(l1, l0)
+    b = AD.Problem(d, steps=90, objective="dp", window=30)
+    J2, g2, l2 = b.value_and_grad()
+    assert J2 == J0 and torch.equal(l2, l0)
+    assert np.allclose(g2, g0, rtol=1e-12, atol=0.0), (g0, g2)
+    a.close()
+    b.close()
+
+
 def test_autograd_function_and_finite_differences(torch):
     say("autograd")
     d = droplet_instance(48, 48, 0, R=12, g=1e-5)
