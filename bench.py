@@ -12,7 +12,9 @@ observable pass (mass drift, finiteness) runs before and after it and is
 timed on its own.
 
 Prints ONE JSON line with MLUPS, the HBM roofline of the dominant kernel
-(HIP-event timing on the context's stream), a measured copy-kernel ceiling
+(its average launch duration over the timed region, HIP events on the
+context's stream; the same kernel launched on its own beside it), a
+measured copy-kernel ceiling
 and the CPU oracle's rate on a bounded sample of the same workload.  Beside
 it, on the same GPU:
   * "batched": 96 uneven static-droplet instances (24 each of 64^2, 128^2,
@@ -21,9 +23,10 @@ it, on the same GPU:
     pressure jump against the FP64 oracle's (stored expected values);
   * "adjoint": the 512 x 512 droplet array (16 droplets, R = 20, g_x = 1e-6):
     plain forward MLUPS, and forward + reverse-mode gradient of the pressure
-    jump with respect to (G1, G2, G_AB, tau_A, tau_B) with checkpoints every
-    200 steps, as MLUPS of the simulated steps, plus the adjoint kernels'
-    timings and algorithmic bandwidth;
+    jump with respect to (G1, G2, G_AB, tau_A, tau_B), every state of the
+    4000-step run kept in HBM when it fits (else checkpoint windows), as MLUPS
+    of the simulated steps, plus the adjoint kernels' timings and
+    algorithmic bandwidth;
   * "emulsion": the walled 4096 x 512 emulsion (200 droplets, R = 16,
     g_x = 1e-6) at viscosity ratios nu_A / nu_B in {0.5, 1, 2, 4}: MLUPS and
     the relative effective viscosity Q(0) / Q(Phi) after 50000 steps.
@@ -53,36 +56,34 @@ B_PER_LU = 160.0
 KERNEL_B_PER_LU = 144.0
 DOMINANT = "k_fused_step"
 
-# HBM bytes per k_fused_step launch on this workload from rocprofv3 --pmc
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same
-# library), per strip plan (width, height, workgroups per CU), valid only for
-# the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "e86abe41d0bed219",
-                    "plans": {(58, 74, 0): (160251.8 * 2.0 * 1024, 295557.5 * 1024),
-                              (58, 76, 0): (160906.6 * 2.0 * 1024, 295693.1 * 1024),
-                              (58, 78, 0): (160902.8 * 2.0 * 1024, 295661.8 * 1024),
-                              (58, 80, 0): (159643.6 * 2.0 * 1024, 295677.1 * 1024),
-                              (506, 41, 0): (170375.4 * 2.0 * 1024, 295425.9 * 1024),
-                              (250, 37, 0): (172945.3 * 2.0 * 1024, 296246.4 * 1024),
-                              (122, 48, 0): (168346.0 * 2.0 * 1024, 296727.3 * 1024),
-                              (58, 64, 0): (163035.2 * 2.0 * 1024, 297303.5 * 1024),
-                              (48, 90, 0): (159362.1 * 2.0 * 1024, 294912.0 * 1024),
-                              (112, 52, 0): (167344.0 * 2.0 * 1024, 294913.7 * 1024),
-                              (122, 46, 0): (168568.3 * 2.0 * 1024, 296892.4 * 1024),
-                              (240, 37, 0): (174749.8 * 2.0 * 1024, 294921.4 * 1024),
-                              (240, 38, 0): (174132.0 * 2.0 * 1024, 294920.5 * 1024),
-                              (240, 40, 0): (173506.6 * 2.0 * 1024, 294920.4 * 1024),
-                              (250, 40, 0): (171892.1 * 2.0 * 1024, 296156.8 * 1024),
-                              (496, 42, 0): (170660.6 * 2.0 * 1024, 294912.3 * 1024),
-                              (506, 42, 0): (169468.1 * 2.0 * 1024, 295321.2 * 1024),
-                              (58, 40, 0): (173903.9 * 2.0 * 1024, 300025.7 * 1024),
-                              (58, 37, 0): (175822.0 * 2.0 * 1024, 300491.2 * 1024)}}
+# HBM bytes per k_fused_step launch from rocprofv3 --pmc (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same library), per
+# workload and strip plan (workload, width, height, workgroups per CU, full
+# rows), valid only for the kernel sources they were measured on.
+MEASURED_TRAFFIC = {"src_sha256_16": "ecadad9a9d00d1fc",
+                    "plans": {("batched", 0, 26, 0, 1): (128896.6 * 2.0 * 1024, 207365.0 * 1024),
+                              ("batched", 58, 64, 0, 0): (113985.3 * 2.0 * 1024, 207493.8 * 1024),
+                              ("spinodal", 58, 37, 0, 0): (175715.8 * 2.0 * 1024, 300426.8 * 1024),
+                              ("spinodal", 58, 40, 0, 0): (173802.6 * 2.0 * 1024, 300079.0 * 1024),
+                              ("spinodal", 58, 64, 0, 0): (163104.6 * 2.0 * 1024, 297358.1 * 1024),
+                              ("spinodal", 58, 74, 0, 0): (160272.1 * 2.0 * 1024, 295567.7 * 1024),
+                              ("spinodal", 58, 76, 0, 0): (160872.9 * 2.0 * 1024, 295706.1 * 1024),
+                              ("spinodal", 58, 78, 0, 0): (160872.9 * 2.0 * 1024, 295704.1 * 1024),
+                              ("spinodal", 58, 80, 0, 0): (159595.4 * 2.0 * 1024, 295607.3 * 1024),
+                              ("spinodal", 122, 46, 0, 0): (168389.8 * 2.0 * 1024, 296732.5 * 1024),
+                              ("spinodal", 122, 48, 0, 0): (168049.0 * 2.0 * 1024, 296580.8 * 1024),
+                              ("spinodal", 240, 37, 0, 0): (173836.6 * 2.0 * 1024, 294921.7 * 1024),
+                              ("spinodal", 240, 38, 0, 0): (173174.8 * 2.0 * 1024, 294919.4 * 1024),
+                              ("spinodal", 250, 37, 0, 0): (172537.3 * 2.0 * 1024, 295932.5 * 1024),
+                              ("spinodal", 506, 41, 0, 0): (170362.8 * 2.0 * 1024, 295199.1 * 1024),
+                              ("spinodal", 506, 42, 0, 0): (169459.0 * 2.0 * 1024, 295073.4 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
 
-def measured_traffic(strip_width, strip_height, balance):
-    """Counter-based bytes per launch, or None once the kernel or its launch plan changed."""
+def measured_traffic(lbm, sim, workload):
+    """Counter-based bytes per launch under sim's current strip plan, or None
+    once the kernel or the plan differs from the measured ones."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -91,7 +92,11 @@ def measured_traffic(strip_width, strip_height, balance):
     t = MEASURED_TRAFFIC
     if h.hexdigest()[:16] != t["src_sha256_16"]:
         return None
-    plan = t["plans"].get((strip_width, 0 if balance else strip_height, balance))
+    fr = lbm.lbm_get_full_rows(sim.ctx)
+    bal = lbm.lbm_get_balance(sim.ctx)
+    key = (workload, 0 if fr else lbm.lbm_get_strip_width(sim.ctx),
+           0 if bal else lbm.lbm_get_tiling(sim.ctx), bal, fr)
+    plan = t["plans"].get(key)
     return None if plan is None else round(plan[0] + plan[1])
 
 
@@ -168,8 +173,10 @@ def bench_batched(torch, lbm, tune, W, steps):
     sim.prepare()
     ms = timed(torch, sim.stream, lambda: sim.step(steps))
     obs, _ = sim.observables()
-    prof = dict(lbm.lbm_profile_step(sim.ctx, 50))
-    k_ms = prof["k_fused_step"]
+    # the timed region holds only launches of the step kernel, one per step
+    k_ms = ms / steps
+    k_iso = dict(lbm.lbm_profile_step(sim.ctx, 50))["k_fused_step"]
+    traffic = measured_traffic(lbm, sim, "batched")
     lap = None
     gold = golden_batched_laplace() if steps == BATCHED_ORACLE_STEPS else None
     if gold is not None and len(gold) == len(ws):
@@ -184,9 +191,11 @@ def bench_batched(torch, lbm, tune, W, steps):
            "instances": len(ws), "nodes": nodes, "steps": steps,
            "value": round(nodes * steps / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
            "ms_per_step": round(ms / steps, 5), "strip_height": tuning,
-           "kernel_ms": round(k_ms, 5),
+           "kernel_ms": round(k_ms, 5), "kernel_ms_isolated": round(k_iso, 5),
            "alg_gbps": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9, 1),
            "roofline_frac": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "traffic": traffic,
+           "traffic_b_per_lu": None if traffic is None else round(traffic / nodes, 1),
            "laplace_error": lap,
            "all_finite": all(o["finite"] for o in obs)}
     sim.close()
@@ -381,9 +390,11 @@ def main():
     obs1, _ = sim.observables()
     obs_ms = (time.perf_counter() - o0) * 1e3
 
-    # per-kernel durations on the context's stream (HIP events)
+    # the dominant kernel's average launch duration over the timed region
+    # (it holds nothing but one launch of it per step), and the same kernel
+    # in 100 back-to-back launches on its own (HIP events on the same stream)
+    k_ms = ms_per_step
     prof = dict(lbm.lbm_profile_step(sim.ctx, 100))
-    k_ms = prof[DOMINANT]
     achieved = B_PER_LU * N / (k_ms * 1e-3) / 1e9
 
     # achievable HBM bandwidth: the library's copy kernel over 2 x 1 GiB
@@ -408,8 +419,7 @@ def main():
     emul = bench_emulsion(torch, lbm, tune, W, a.emulsion_steps) if a.emulsion_steps > 0 else None
 
     cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
-    traffic = measured_traffic(lbm.lbm_get_strip_width(sim.ctx), lbm.lbm_get_tiling(sim.ctx),
-                               lbm.lbm_get_balance(sim.ctx))
+    traffic = measured_traffic(lbm, sim, "spinodal")
 
     mass_drift = [abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] for k in range(2)]
     out = {
@@ -435,7 +445,8 @@ def main():
                      "kernel": DOMINANT, "bytes_per_lu": B_PER_LU,
                      "kernel_bytes_per_lu": KERNEL_B_PER_LU,
                      "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / B_PER_LU, 1),
-                     "kernel_ms": round(k_ms, 5)},
+                     "kernel_ms": round(k_ms, 5),
+                     "kernel_ms_isolated": round(prof[DOMINANT], 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
         "alg_gbps_whole_step": round(mlups * 1e6 * B_PER_LU / 1e9, 1),
         "copy_kernel_gbps": round(copy_gbps, 1),
