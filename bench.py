@@ -59,7 +59,8 @@ DOMINANT = "k_fused_step"
 # HBM bytes per k_fused_step launch from rocprofv3 --pmc (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same library), per
 # workload and strip plan (workload, width, height, workgroups per CU, full
-# rows), valid only for the kernel sources they were measured on.
+# rows; a trailing 2 for two steps per launch, whose bytes cover two steps),
+# valid only for the kernel sources they were measured on.
 MEASURED_TRAFFIC = {"src_sha256_16": "ecadad9a9d00d1fc",
                     "plans": {("batched", 0, 26, 0, 1): (128896.6 * 2.0 * 1024, 207365.0 * 1024),
                               ("batched", 58, 64, 0, 0): (113985.3 * 2.0 * 1024, 207493.8 * 1024),
@@ -96,6 +97,8 @@ def measured_traffic(lbm, sim, workload):
     bal = lbm.lbm_get_balance(sim.ctx)
     key = (workload, 0 if fr else lbm.lbm_get_strip_width(sim.ctx),
            0 if bal else lbm.lbm_get_tiling(sim.ctx), bal, fr)
+    if lbm.lbm_get_two_step(sim.ctx):
+        key = key + (2,)
     plan = t["plans"].get(key)
     return None if plan is None else round(plan[0] + plan[1])
 
@@ -112,6 +115,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="strip height (0: autotune)")
     ap.add_argument("--width", type=int, default=0, help="strip width with --chunk (0: 58)")
     ap.add_argument("--balance", type=int, default=0, help="with --width: workgroups per CU")
+    ap.add_argument("--two-step", type=int, default=0,
+                    help="with --chunk: two steps per launch (--width at most 52)")
     ap.add_argument("--batched-steps", type=int, default=5000, help="0 skips the batched form")
     ap.add_argument("--emulsion-steps", type=int, default=50000,
                     help="0 skips the emulsion viscosity-ratio sweep")
@@ -175,7 +180,7 @@ def bench_batched(torch, lbm, tune, W, steps):
     obs, _ = sim.observables()
     # the timed region holds only launches of the step kernel, one per step
     k_ms = ms / steps
-    k_iso = dict(lbm.lbm_profile_step(sim.ctx, 50))["k_fused_step"]
+    k_iso = tune.step_ms(sim, 50)
     traffic = measured_traffic(lbm, sim, "batched")
     lap = None
     gold = golden_batched_laplace() if steps == BATCHED_ORACLE_STEPS else None
@@ -194,8 +199,10 @@ def bench_batched(torch, lbm, tune, W, steps):
            "kernel_ms": round(k_ms, 5), "kernel_ms_isolated": round(k_iso, 5),
            "alg_gbps": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9, 1),
            "roofline_frac": round(B_PER_LU * nodes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "steps_per_launch": 2 if lbm.lbm_get_two_step(sim.ctx) else 1,
            "traffic": traffic,
-           "traffic_b_per_lu": None if traffic is None else round(traffic / nodes, 1),
+           "traffic_b_per_lu": None if traffic is None else
+           round(traffic / nodes / (2 if lbm.lbm_get_two_step(sim.ctx) else 1), 1),
            "laplace_error": lap,
            "all_finite": all(o["finite"] for o in obs)}
     sim.close()
@@ -219,9 +226,10 @@ def bench_emulsion(torch, lbm, tune, W, steps, ratios=(0.5, 1.0, 2.0, 4.0)):
             sim = lbm.Sim([lbm.workload_instance(w)], device="cuda:0")
             if plan is None:
                 t = tune.tune(sim, use_cache=False)
-                plan = {k: t.get(k) for k in ("width", "best", "balance", "full_rows")}
+                plan = {k: t.get(k) for k in ("width", "best", "balance", "full_rows", "two_step")}
             else:
-                tune.apply(sim, plan["width"], plan["best"], plan["balance"], plan["full_rows"])
+                tune.apply(sim, plan["width"], plan["best"], plan["balance"], plan["full_rows"],
+                           plan["two_step"])
             sim.prepare()
             ms = timed(torch, sim.stream, lambda: sim.step(steps))
             obs, _ = sim.observables()
@@ -256,7 +264,7 @@ def bench_adjoint(torch, lbm, W, steps, window):
     store_gb = prob.state_bytes() * min(window_used, steps) * (1 if window_used >= steps else 2) / 1e9
     for s in (prob.sim, prob.rec):  # forward context and window re-run context
         tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0),
-                   tuning.get("full_rows", 0))
+                   tuning.get("full_rows", 0), tuning.get("two_step", 0))
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -286,7 +294,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
                         "couplings (3.0, -7.4, 6.4), tau (1.0, 0.6)",
             "steps": steps, "window": window_used, "store_gb": round(store_gb, 2),
             "objective": "J_dp (smooth pressure jump)",
-            "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance", "full_rows")},
+            "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance", "full_rows",
+                                                      "two_step")},
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),
             "J": J, "grad_theta": {n: float(v) for n, v in zip(lbm.THETA_NAMES, g)},
@@ -357,8 +366,9 @@ def main():
 
     # strip height: autotuned (untimed) unless given
     if a.chunk > 0 or a.balance > 0:
-        tune.apply(sim, a.width or 58, a.chunk, a.balance)
-        tuning = {"best": a.chunk, "width": a.width or 58, "balance": a.balance}
+        tune.apply(sim, a.width or 58, a.chunk, a.balance, 0, a.two_step)
+        tuning = {"best": a.chunk, "width": a.width or 58, "balance": a.balance, "full_rows": 0,
+                  "two_step": a.two_step}
     else:
         tuning = tune.tune(sim, use_cache=False)
 
@@ -393,9 +403,11 @@ def main():
     # the dominant kernel's average launch duration over the timed region
     # (it holds nothing but one launch of it per step), and the same kernel
     # in 100 back-to-back launches on its own (HIP events on the same stream)
-    k_ms = ms_per_step
+    spl = 2 if lbm.lbm_get_two_step(sim.ctx) else 1  # steps per launch
+    k_ms = ms_per_step * spl
     prof = dict(lbm.lbm_profile_step(sim.ctx, 100))
-    achieved = B_PER_LU * N / (k_ms * 1e-3) / 1e9
+    kname = "k_fused_step2" if spl == 2 else DOMINANT
+    achieved = spl * B_PER_LU * N / (k_ms * 1e-3) / 1e9
 
     # achievable HBM bandwidth: the library's copy kernel over 2 x 1 GiB
     nbytes = 1 << 30
@@ -441,12 +453,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE)",
-                     "algorithmic_bytes": B_PER_LU * N,
-                     "kernel": DOMINANT, "bytes_per_lu": B_PER_LU,
+                     "algorithmic_bytes": spl * B_PER_LU * N, "steps_per_launch": spl,
+                     "kernel": kname, "bytes_per_lu": B_PER_LU,
                      "kernel_bytes_per_lu": KERNEL_B_PER_LU,
                      "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / B_PER_LU, 1),
                      "kernel_ms": round(k_ms, 5),
-                     "kernel_ms_isolated": round(prof[DOMINANT], 5)},
+                     "kernel_ms_isolated": round(prof[kname], 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
         "alg_gbps_whole_step": round(mlups * 1e6 * B_PER_LU / 1e9, 1),
         "copy_kernel_gbps": round(copy_gbps, 1),

@@ -203,8 +203,10 @@ int lbm_copy_probe(lbm_ctx *ctx, void *dst_dev, const void *src_dev, uint64_t nb
  * times back to back on the context's stream between two HIP events; ms[j]
  * receives the average duration of kernel j in milliseconds and names[j]
  * (if names is not NULL) a static string naming it.  *n_kernels receives the
- * number of kernels per step (at most max_k are written).  The state is left
- * unchanged.  Synchronises the stream. */
+ * number of kernels per step (at most max_k are written).  In two-step mode
+ * (lbm_set_two_step) the kernel timed is the two-step one, "k_fused_step2",
+ * and ms[0] covers two steps.  The state is left unchanged.  Synchronises
+ * the stream. */
 int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, const char **names,
                      int32_t *n_kernels);
 
@@ -246,6 +248,20 @@ int32_t lbm_get_balance(const lbm_ctx *ctx);
  * stream and discards captured graphs. */
 int lbm_set_full_rows(lbm_ctx *ctx, int32_t on);
 int32_t lbm_get_full_rows(const lbm_ctx *ctx);
+
+/* Two steps per launch (on = 1): lbm_step then advances every instance two
+ * time steps (Eqs. 1-9, twice) per launch of a second kernel that keeps the
+ * intermediate state of each strip on chip, so the populations cross HBM
+ * once per two steps; an odd remaining step runs alone.  Every node goes
+ * through exactly the operations of two single steps: the states equal
+ * those of the single-step kernel bit for bit.  It needs one-wavefront
+ * strips of at most 52 output columns (lbm_set_strip_width(ctx, c) with
+ * c <= 52, uniform or balanced, no full rows): LBM_EUNSUPPORTED otherwise,
+ * and, while it is on, for the plan setters that would leave such strips.
+ * Only lbm_step changes; recording, the adjoint and the observables run
+ * the single step.  Discards captured graphs. */
+int lbm_set_two_step(lbm_ctx *ctx, int32_t on);
+int32_t lbm_get_two_step(const lbm_ctx *ctx);
 
 /* Workgroups of one launch of the fused step under the current strip plan. */
 int32_t lbm_get_workgroups(const lbm_ctx *ctx);

@@ -422,6 +422,7 @@ struct lbm_ctx {
     int width = DEFAULT_WIDTH;
     int balance = 0;   // workgroups per CU of a balanced plan (0: uniform chunks)
     int full_rows = 0; // 1: full-row plan of uniform chunks (lattice widths 64 k)
+    int two_step = 0;  // 1: lbm_step advances two steps per launch (k_fused_step2)
     int ncu = 256;     // compute units of the device
     // rho[par] holds the densities of the state in f[par] (the plain step
     // does not write them; ensure_rho computes them when a kernel reads them)
@@ -609,13 +610,28 @@ static int ensure_rho(lbm_ctx *ctx)
     return LBM_OK;
 }
 
+// n steps as launches on stream st: pairs of steps in one launch each in
+// two-step mode (the last odd step alone), else one launch per step; every
+// launch moves the state to the other buffer
+static hipError_t launch_steps(lbm_ctx *ctx, int64_t n, int &par, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (ctx->two_step)
+        for (; n >= 2 && e == hipSuccess; n -= 2) {
+            e = launch_step2(ctx->dev, par, st);
+            par ^= 1;
+        }
+    for (; n > 0 && e == hipSuccess; --n) {
+        e = launch_step(ctx->dev, par, st);
+        par ^= 1;
+    }
+    return e;
+}
+
 static int step_eager(lbm_ctx *ctx, int64_t n, hipStream_t st)
 {
-    for (int64_t s = 0; s < n; ++s) {
-        hipError_t e = launch_step(ctx->dev, ctx->par, st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
-        ctx->par ^= 1;
-    }
+    hipError_t e = launch_steps(ctx, n, ctx->par, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
     return LBM_OK;
 }
 
@@ -624,12 +640,9 @@ static int ensure_graph(lbm_ctx *ctx, int par)
     if (ctx->graph[par]) return LBM_OK;
     if (!ctx->cap) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
     HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipSuccess;
     int p = par;
-    for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s) {
-        le = launch_step(ctx->dev, p, ctx->cap);
-        p ^= 1;
-    }
+    // GRAPH_STEPS is even: in either mode the graph ends on the parity it starts from
+    hipError_t le = launch_steps(ctx, GRAPH_STEPS, p, ctx->cap);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(ctx->cap, &g);
     if (le != hipSuccess) {
@@ -841,9 +854,14 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
     int rc = LBM_OK;
     ctx->rho_ok[ctx->par ^ 1] = false;  // the launches overwrite f[par ^ 1]
     for (int j = 0; j < N_STEP_KERNELS && j < max_k && rc == LBM_OK; ++j) {
-        hipError_t e = launch_step_kernel(ctx->dev, j, ctx->par, st);  // warm-up
+        // in two-step mode the step kernel is the two-step one (two steps per launch)
+        auto launch = [&]() {
+            return ctx->two_step ? launch_step2(ctx->dev, ctx->par, st)
+                                 : launch_step_kernel(ctx->dev, j, ctx->par, st);
+        };
+        hipError_t e = launch();  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, st);
-        for (int r = 0; r < nrep && e == hipSuccess; ++r) e = launch_step_kernel(ctx->dev, j, ctx->par, st);
+        for (int r = 0; r < nrep && e == hipSuccess; ++r) e = launch();
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float t = 0.f;
@@ -853,15 +871,34 @@ int lbm_profile_step(lbm_ctx *ctx, int32_t nrep, int32_t max_k, double *ms, cons
             break;
         }
         ms[j] = (double)t / nrep;
-        if (names) names[j] = step_kernel_name(j);
+        if (names) names[j] = ctx->two_step ? "k_fused_step2" : step_kernel_name(j);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
 }
 
+static void drop_graphs(lbm_ctx *ctx)
+{
+    for (int i = 0; i < 2; ++i)
+        if (ctx->graph[i]) {
+            (void)hipGraphExecDestroy(ctx->graph[i]);
+            ctx->graph[i] = nullptr;
+        }
+}
+
+// a strip plan the two-step kernel can run: one-wavefront strips of at most
+// SW2 output columns
+static bool two_step_plan(int cols, int full_rows)
+{
+    return !full_rows && strip_waves(cols) == 1 && cols <= SW2;
+}
+
 static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance, int full_rows = 0)
 {
+    if (ctx->two_step && !two_step_plan(cols, full_rows))
+        return fail(ctx, LBM_EUNSUPPORTED, "two steps per launch need one-wavefront strips of at "
+                                           "most 52 columns (lbm_set_two_step(ctx, 0) first)");
     const int frw = full_rows ? fullrow_waves(ctx->params.data(), ctx->n_inst) : 0;
     if (full_rows && !frw)
         return fail(ctx, LBM_EUNSUPPORTED, "full rows need every lattice width a multiple of 64, at most 512");
@@ -886,11 +923,7 @@ static int set_strips(lbm_ctx *ctx, int rows, int cols, int balance, int full_ro
     ctx->width = cols;
     ctx->balance = full_rows ? 0 : balance;
     ctx->full_rows = full_rows;
-    for (int i = 0; i < 2; ++i)
-        if (ctx->graph[i]) {
-            (void)hipGraphExecDestroy(ctx->graph[i]);
-            ctx->graph[i] = nullptr;
-        }
+    drop_graphs(ctx);
     return LBM_OK;
 }
 
@@ -910,6 +943,20 @@ int lbm_set_full_rows(lbm_ctx *ctx, int32_t on)
 }
 
 int32_t lbm_get_full_rows(const lbm_ctx *ctx) { return ctx ? ctx->full_rows : -1; }
+
+int lbm_set_two_step(lbm_ctx *ctx, int32_t on)
+{
+    CTX_CHECK(ctx);
+    if (on != 0 && on != 1) return fail(ctx, LBM_EINVAL, "on must be 0 or 1");
+    if (on && !two_step_plan(ctx->width, ctx->full_rows))
+        return fail(ctx, LBM_EUNSUPPORTED, "two steps per launch need one-wavefront strips of at "
+                                           "most 52 columns");
+    if (on != ctx->two_step) drop_graphs(ctx);
+    ctx->two_step = on;
+    return LBM_OK;
+}
+
+int32_t lbm_get_two_step(const lbm_ctx *ctx) { return ctx ? ctx->two_step : -1; }
 
 int lbm_set_strip_width(lbm_ctx *ctx, int32_t cols)
 {

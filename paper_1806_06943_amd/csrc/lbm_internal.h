@@ -36,8 +36,15 @@ struct Dev {
 constexpr int strip_waves(int cols) { return cols <= 58 ? 1 : cols <= 122 ? 2 : cols <= 250 ? 4 : 8; }
 constexpr int MAX_STRIP_COLS = 8 * 64 - 6;
 
+// output columns of a one-wavefront strip of the two-step kernel (six
+// columns of halo on either side)
+constexpr int SW2 = SW - 4 * (HALO + 1);
+
 hipError_t launch_init(const Dev &d, const double *const *rho0s, hipStream_t st);
 hipError_t launch_step(const Dev &d, int par, hipStream_t st);
+// two steps in one launch (one-wavefront strips of at most SW2 output
+// columns, no full rows): f[par] -> f[par ^ 1]
+hipError_t launch_step2(const Dev &d, int par, hipStream_t st);
 // Options of one launch of the fused step: buffers that replace one
 // instance's ping-pong pair (a window recorded in place; inst < 0: none),
 // and whether the launch writes rho(t + 1) of every instance (wrho 1) or of

@@ -113,6 +113,9 @@ def lib() -> ctypes.CDLL:
         L.lbm_set_full_rows.argtypes = [vp, ctypes.c_int32]
         L.lbm_get_full_rows.argtypes = [vp]
         L.lbm_get_full_rows.restype = ctypes.c_int32
+        L.lbm_set_two_step.argtypes = [vp, ctypes.c_int32]
+        L.lbm_get_two_step.argtypes = [vp]
+        L.lbm_get_two_step.restype = ctypes.c_int32
         L.lbm_get_workgroups.argtypes = [vp]
         L.lbm_get_workgroups.restype = ctypes.c_int32
         L.lbm_get_strip_width.argtypes = [vp]
@@ -292,6 +295,14 @@ def lbm_set_full_rows(ctx, on: int):
 
 def lbm_get_full_rows(ctx) -> int:
     return int(lib().lbm_get_full_rows(ctx))
+
+
+def lbm_set_two_step(ctx, on: int):
+    _check(lib().lbm_set_two_step(ctx, int(on)), ctx)
+
+
+def lbm_get_two_step(ctx) -> int:
+    return int(lib().lbm_get_two_step(ctx))
 
 
 def lbm_get_workgroups(ctx) -> int:

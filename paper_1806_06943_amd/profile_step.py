@@ -4,8 +4,9 @@ Builds the seeded workload (the same generators as the tests and the
 benchmark), applies the strip plan (or tunes it), then times `--launches`
 back-to-back launches of the step's kernel on the context's stream with HIP
 events (lbm_profile_step) and prints the plan, the workgroup count and the
-average launch time.  Under ``rocprofv3 --pmc ...`` every launch is one
-dispatch of the counters, so the per-dispatch averages describe this plan.
+average time per step (a two-step launch counts as two steps).  Under
+``rocprofv3 --pmc ...`` every launch is one dispatch of the counters, so the
+per-dispatch averages describe this plan.
 
     python -m paper_1806_06943_amd.profile_step --workload batched --width 58 --chunk 64
 """
@@ -40,6 +41,8 @@ def main():
     ap.add_argument("--balance", type=int, default=0, help="workgroups per CU with --width")
     ap.add_argument("--full-rows", action="store_true",
                     help="full-row plan of --chunk rows (lattice widths multiples of 64)")
+    ap.add_argument("--two-step", action="store_true",
+                    help="two steps per launch (k_fused_step2; --width at most 52)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also launch the library's copy kernel over this many bytes "
                          "(--launches times): the calibration of traffic counters")
@@ -49,18 +52,18 @@ def main():
     if a.full_rows:
         tune.apply(sim, 0, a.chunk, 0, 1)
     elif a.width > 0:
-        tune.apply(sim, a.width, a.chunk, a.balance)
+        tune.apply(sim, a.width, a.chunk, a.balance, 0, 1 if a.two_step else 0)
     else:
         t = tune.tune(sim, use_cache=False)
         print(f"tuned: width {t['width']} height {t['best']} balance {t['balance']} "
-              f"full rows {t['full_rows']}", flush=True)
+              f"full rows {t['full_rows']} two steps {t['two_step']}", flush=True)
     sim.step(20)
-    ms = dict(lbm.lbm_profile_step(sim.ctx, a.launches))["k_fused_step"]
+    ms = tune.step_ms(sim, a.launches)
     nodes = sum(w.nx * w.ny for w in ws)
     print(f"{a.workload}: {len(ws)} instances, {nodes} nodes, plan {lbm.lbm_get_strip_width(sim.ctx)} x "
           f"{lbm.lbm_get_tiling(sim.ctx)} balance {lbm.lbm_get_balance(sim.ctx)} "
-          f"full rows {lbm.lbm_get_full_rows(sim.ctx)}, "
-          f"{lbm.lbm_get_workgroups(sim.ctx)} workgroups: {ms:.5f} ms per launch, "
+          f"full rows {lbm.lbm_get_full_rows(sim.ctx)} two steps {lbm.lbm_get_two_step(sim.ctx)}, "
+          f"{lbm.lbm_get_workgroups(sim.ctx)} workgroups: {ms:.5f} ms per step, "
           f"{nodes / (ms * 1e-3) / 1e6:.1f} MLUPS, {160.0 * nodes / (ms * 1e-3) / 1e9:.1f} GB/s at "
           f"160 B per lattice update", flush=True)
     if a.copy_bytes > 0:

@@ -15,7 +15,11 @@ the smallest height whose launch has at most k workgroups per compute unit
 (a launch just past such a multiple leaves most compute units idle for its
 last round of workgroups).  Contexts whose lattice widths are all multiples
 of 64 (at most 512) also time the full-row plans (lbm_set_full_rows) at the
-same heights.
+same heights.  With two_step=True the two-step kernel (lbm_set_two_step:
+two time steps per launch, one-wavefront strips of at most 52 columns) is
+timed as well, at widths 52 and 48; a two-step launch counts as two steps.
+It is off by default: on this GPU it has not been faster than the single
+step on any workload measured.
 """
 from __future__ import annotations
 
@@ -30,13 +34,15 @@ MAX_HEIGHT = 65535  # and the largest
 # (output columns per strip): one wavefront per strip, balanced / aligned,
 # then strips of 2, 4 and 8 wavefronts, balanced / aligned
 WIDTHS = (58, 48, 122, 112, 250, 240, 506, 496)
+# strip widths of the two-step kernel (balanced, aligned)
+WIDTHS2 = (52, 48)
 CACHE = os.environ.get("LBM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
                                                         "lbm_tiling.json"))
 
 
 def _key(sim, arch: str) -> str:
     shapes = sorted({(p.nx, p.ny) for p in sim.params})
-    return f"v4|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
+    return f"v5|{arch}|n={sim.n_inst}|" + ",".join(f"{a}x{b}" for a, b in shapes[:8]) + \
         (f"|+{len(shapes) - 8}" if len(shapes) > 8 else "")
 
 
@@ -50,10 +56,12 @@ def _arch(sim) -> str:
 BALANCES = (1, 2, 3, 4)
 
 
-def apply(sim, width: int, height: int, balance: int = 0, full_rows: int = 0):
+def apply(sim, width: int, height: int, balance: int = 0, full_rows: int = 0, two_step: int = 0):
     """Strip width, then either uniform chunks of `height` rows or, if balance > 0,
     the balanced plan with `balance` workgroups per compute unit; with
-    full_rows, the full-row plan of chunks of `height` rows (width unused)."""
+    full_rows, the full-row plan of chunks of `height` rows (width unused);
+    with two_step, two steps per launch on that plan."""
+    lbm.lbm_set_two_step(sim.ctx, 0)
     if full_rows:
         lbm.lbm_set_tiling(sim.ctx, int(height))
         lbm.lbm_set_full_rows(sim.ctx, 1)
@@ -63,6 +71,17 @@ def apply(sim, width: int, height: int, balance: int = 0, full_rows: int = 0):
         lbm.lbm_set_balance(sim.ctx, int(balance))
     else:
         lbm.lbm_set_tiling(sim.ctx, int(height))
+    if two_step:
+        lbm.lbm_set_two_step(sim.ctx, 1)
+
+
+def step_ms(sim, nrep: int) -> float:
+    """Milliseconds per step of the context's step kernel launched nrep times
+    (lbm_profile_step; a two-step launch counts as two steps)."""
+    prof = dict(lbm.lbm_profile_step(sim.ctx, nrep))
+    if "k_fused_step2" in prof:
+        return prof["k_fused_step2"] / 2.0
+    return prof["k_fused_step"]
 
 
 def full_rows_possible(sim) -> bool:
@@ -111,7 +130,7 @@ def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX, full_rows: i
 
 
 def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
-         widths=WIDTHS, balances=BALANCES) -> dict:
+         widths=WIDTHS, balances=BALANCES, two_step: bool = False) -> dict:
     """Pick the fastest strip shape for sim's context; returns the timings."""
     arch = _arch(sim)
     key = _key(sim, arch)
@@ -122,32 +141,37 @@ def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
                 cache = json.load(fh)
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache and "full_rows" in cache[key]:
+    if use_cache and key in cache and "two_step" in cache[key]:
         e = cache[key]
-        apply(sim, e["width"], e["best"], e["balance"], e["full_rows"])
+        apply(sim, e["width"], e["best"], e["balance"], e["full_rows"], e["two_step"])
         return e
     times = {}
     ncu = _ncu(sim)
+
+    def timed(key, *plan):
+        apply(sim, *plan)
+        step_ms(sim, 3)  # warm-up
+        times[key] = step_ms(sim, nrep)
+
     for wdt in widths:
         for h in sorted(set(candidates) | set(fitted_heights(sim, wdt, ncu))):
-            apply(sim, wdt, h)
-            lbm.lbm_profile_step(sim.ctx, 3)  # warm-up
-            times[(wdt, h, 0)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+            timed((wdt, h, 0, 0), wdt, h)
         for b in balances:
-            apply(sim, wdt, 0, b)
-            lbm.lbm_profile_step(sim.ctx, 3)
-            times[(wdt, 0, b)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
+            timed((wdt, 0, b, 0), wdt, 0, b)
+    for wdt in (WIDTHS2 if two_step else ()):
+        for h in sorted(set(candidates) | set(fitted_heights(sim, wdt, ncu))):
+            timed((wdt, h, 0, 1), wdt, h, 0, 0, 1)
+        for b in balances:
+            timed((wdt, 0, b, 1), wdt, 0, b, 0, 1)
     if full_rows_possible(sim):  # width 0 marks a full-row plan
         for h in sorted(set(candidates) | set(fitted_heights(sim, 58, ncu, full_rows=1))):
-            apply(sim, 0, h, 0, 1)
-            lbm.lbm_profile_step(sim.ctx, 3)
-            times[(0, h, 0)] = dict(lbm.lbm_profile_step(sim.ctx, nrep))["k_fused_step"]
-    bw, bh, bb = min(times, key=times.get)
+            timed((0, h, 0, 0), 0, h, 0, 1)
+    bw, bh, bb, ts = min(times, key=times.get)
     fr = 1 if bw == 0 else 0
-    apply(sim, bw, bh, bb, fr)
-    entry = {"best": bh, "width": bw, "balance": bb, "full_rows": fr,
-             "ms": {(f"fr{h}" if w == 0 else f"{w}x{h}" if b == 0 else f"{w}xbal{b}"): v
-                    for (w, h, b), v in times.items()}}
+    apply(sim, bw, bh, bb, fr, ts)
+    entry = {"best": bh, "width": bw, "balance": bb, "full_rows": fr, "two_step": ts,
+             "ms": {("2s" if t else "") + (f"fr{h}" if w == 0 else f"{w}x{h}" if b == 0 else f"{w}xbal{b}"): v
+                    for (w, h, b, t), v in times.items()}}
     if use_cache:
         cache[key] = entry
         try:
@@ -170,6 +194,7 @@ def _main():
     ap.add_argument("--heights", default="8:72:2", help="start:stop:step")
     ap.add_argument("--balances", default="1,2,3,4")
     ap.add_argument("--nrep", type=int, default=30)
+    ap.add_argument("--two-step", type=int, default=0, help="1: two steps per launch (widths <= 52)")
     a = ap.parse_args()
     ws = W.batched() if a.workload == "batched" else [getattr(W, a.workload)()]
     sim = lbm.Sim([lbm.workload_instance(w) for w in ws])
@@ -178,9 +203,9 @@ def _main():
     for wdt in (int(v) for v in a.widths.split(",")):
         plans = [(h, 0) for h in range(h0, h1, hs)] + [(0, int(b)) for b in a.balances.split(",") if b]
         for h, b in plans:
-            apply(sim, wdt, h, b)
-            lbm.lbm_profile_step(sim.ctx, 3)
-            ms = dict(lbm.lbm_profile_step(sim.ctx, a.nrep))["k_fused_step"]
+            apply(sim, wdt, h, b, 0, a.two_step)
+            step_ms(sim, 3)
+            ms = step_ms(sim, a.nrep)
             rows.append((ms, wdt, h, b))
             print(f"width {wdt:4d} {'balance ' + str(b) if b else 'height ' + str(h):>10s}  "
                   f"workgroups {lbm.lbm_get_workgroups(sim.ctx):6d}  "
