@@ -52,7 +52,8 @@ HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, public figure
 # (16 B).  The roofline fraction is priced at this figure.
 B_PER_LU = 160.0
 # What k_fused_step itself must move: it derives the densities from the
-# populations it loads and writes none, so only the populations (144 B).
+# populations it loads and writes none, so only the populations (144 B);
+# the two-step kernel moves them once per two steps (72 B per update).
 KERNEL_B_PER_LU = 144.0
 DOMINANT = "k_fused_step"
 
@@ -457,8 +458,10 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE)",
                      "algorithmic_bytes": spl * B_PER_LU * N, "steps_per_launch": spl,
                      "kernel": kname, "bytes_per_lu": B_PER_LU,
-                     "kernel_bytes_per_lu": KERNEL_B_PER_LU,
-                     "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / B_PER_LU, 1),
+                     "kernel_bytes_per_lu": KERNEL_B_PER_LU / spl,
+                     "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / spl / B_PER_LU, 1),
+                     "counted_gbps": None if traffic is None else
+                     round(traffic / (k_ms * 1e-3) / 1e9, 1),
                      "kernel_ms": round(k_ms, 5),
                      "kernel_ms_isolated": round(prof[kname], 5)},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},

@@ -4,6 +4,8 @@
 // or many lattices of different sizes alike.
 #include "lbm_internal.h"
 
+#include <type_traits>
+
 namespace lbm {
 
 // ------------------------------------------------------------------ init
@@ -364,11 +366,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         R.psi[1][slot][cl] = pbv;
         R.dev[0][slot][cl] = da;
         R.dev[1][slot][cl] = db;
-        if (FR && cw >= 0) {  // the row's periodic wrap (stencil values only)
-            R.rho[0][slot][cw] = ra;
-            R.rho[1][slot][cw] = rb;
-            R.psi[0][slot][cw] = pa;
-            R.psi[1][slot][cw] = pbv;
+        if constexpr (FR) {
+            if (cw >= 0) {  // the row's periodic wrap (stencil values only)
+                R.rho[0][slot][cw] = ra;
+                R.rho[1][slot][cw] = rb;
+                R.psi[0][slot][cw] = pa;
+                R.psi[1][slot][cw] = pbv;
+            }
         }
     };
 
@@ -566,33 +570,53 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
 }
 
 // ------------------------------------------------------------------ two steps per pass
-// Two time steps in one pass over the lattice (temporal blocking), for
-// one-wavefront strips.  Stage A is the single step above: it loads f(t),
-// collides row c1 and pulls output row o1 = c1 - 1 of f(t+1), which goes to
-// a three-row LDS buffer instead of memory, together with its densities
-// (the sums the step would write as rho(t + 1)) into a second density ring.
-// Stage B then advances f(t+1) the same way, two rows behind (it collides
-// row c2 = o1 - 2, whose five stencil rows are then all in the second ring)
-// and writes f(t+2).  Every node goes through exactly the operations of two
-// single steps, in the same order, so the result equals two launches of
-// k_fused_step bit for bit.  The HBM traffic is that of one step.
-// Lane L owns lattice column X0 - 6 + L: lanes 0 .. wo + 11 load, stage A
-// collides lanes 2 .. wo + 9 and produces f(t+1) for lanes 3 .. wo + 8,
-// stage B collides lanes 5 .. wo + 6 and writes lanes 6 .. wo + 5, the
-// segment's wo <= SW2 output columns.  A segment of ho output rows takes
-// ho + 8 row iterations: stage A collides rows Y0 - 4 .. Y0 + ho + 3 (and
-// loads Y0 - 6 .. Y0 + ho + 5), stage B collides Y0 - 1 .. Y0 + ho.
-// One wavefront per workgroup: LDS is read and written by that wavefront
-// alone, in program order, so no barrier is needed (wg_sync).
+// Two time steps in one pass over the lattice (temporal blocking) as a
+// pipeline of two wavefronts per one-strip workgroup.  Wavefront 0 (stage A)
+// is the single step above: it loads f(t), collides row c1 and pulls output
+// row o1 = c1 - 1 of f(t+1), which goes to LDS instead of memory, together
+// with its densities (the sums the step would write as rho(t + 1)) in a
+// second density ring.  Wavefront 1 (stage B) advances f(t+1) the same way
+// from those rows, one barrier phase and two rows behind, and writes f(t+2).
+// Every node goes through exactly the operations of two single steps, in
+// the same order, so the result equals two launches of k_fused_step bit for
+// bit; the populations cross HBM once per two steps.  Each stage has the
+// registers of one wavefront to itself, and the two wavefronts of a SIMD
+// (two workgroups per SIMD pair) overlap one stage's memory waits with the
+// other's arithmetic.
+// Lane L of either wavefront owns lattice column X0 - 6 + L: stage A loads
+// lanes 0 .. wo + 11, collides lanes 2 .. wo + 9 and produces f(t+1) for
+// lanes 3 .. wo + 8; stage B collides lanes 5 .. wo + 6 and writes lanes
+// 6 .. wo + 5, the segment's wo <= SW2 output columns.  A segment of ho
+// output rows takes ho + 9 phases, one barrier each.  In phase p, stage A
+// collides row Y0 - 4 + p (loading Y0 - 1 + p) and, from p = 2 on, writes
+// row o1(p) = Y0 - 5 + p of f(t+1) to slot p mod 4 and its densities to ring
+// slot p mod 6; stage B collides row o1(p - 3) (p >= 7), whose stencil rows
+// o1(p - 5) .. o1(p - 1) were written in earlier phases, and from p = 9 on
+// writes row Y0 - 9 + p of f(t+2).  Stage B never reads a slot stage A
+// writes in the same phase, and the barrier that ends a phase orders the
+// rest.
+// density ring of f(t+1) in the two-step kernel: six row slots of a
+// one-wavefront strip's columns
+struct RingB6 {
+    static constexpr int NS = 6;
+    static constexpr int W = RingW<1, 0>::W;
+    float rho[2][NS][W];
+    float psi[2][NS][W];
+    float dev[2][NS][W];
+};
+
 template <int FS>
-__global__ __launch_bounds__(64, 1) void k_fused_step2(const KInst *__restrict__ insts,
-                                                       const int4 *__restrict__ segs,
-                                                       const int *__restrict__ first, int par)
+__global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict__ insts,
+                                                        const int4 *__restrict__ segs,
+                                                        const int *__restrict__ first, int par)
 {
-    __shared__ RingW<1, 0> RA, RB;    // density rings of f(t) and of f(t+1)
-    __shared__ float4 FQ[3][4][64];   // f(t+1) rows (slot = row mod 3): four float4 planes
-    __shared__ float2 FQ2[3][64];     // and the float2 plane
-    const int L = (int)threadIdx.x;
+    constexpr int RB6 = RingB6::NS;
+    __shared__ RingW<1, 0> RA;        // densities of f(t): stage A only
+    __shared__ RingB6 RB;             // densities of f(t+1)
+    __shared__ float4 FQ[4][4][64];   // f(t+1) rows: four float4 planes per slot
+    __shared__ float2 FQ2[4][64];     // and the float2 plane
+    const int L = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int sg_begin = first[blockIdx.x], sg_end = first[blockIdx.x + 1];
     for (int sg = sg_begin; sg < sg_end; ++sg) {
     const int4 t = segs[sg];
@@ -602,19 +626,13 @@ __global__ __launch_bounds__(64, 1) void k_fused_step2(const KInst *__restrict__
     const int nx = G.nx, ny = G.ny, walls = G.walls;
     const uint32_t pb = (uint32_t)G.pitch;
     const uint32_t frowb = 72u * pb;
-    const __amdgpu_buffer_rsrc_t fin = make_rsrc(G.f[par], (uint32_t)ny * frowb);
-    const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
     constexpr uint32_t DROP = 0x80000000u;
-    constexpr int H2 = 2 * (HALO + 1);  // columns left of the output per stage pair
-    const int jmax = wo + 2 * H2 - 1;
+    constexpr int H2 = 2 * (HALO + 1);  // columns left of the output for the two stages
     const int X = X0 - H2 + L;
-    const bool outl = (L >= H2) && (L < wo + H2);
-    const uint32_t xl = (uint32_t)wrapi(X, nx);
-    const bool needf = L <= jmax;
-    const uint32_t xf16 = needf ? xl * 16u : DROP, xf8 = needf ? xl * 8u : DROP;
     const int cl = L;                        // ring column of this lane
     const int cs = cl < HALO ? HALO : cl;    // stencil centre (never left of the ring)
     LDS_CHECK((cs + HALO < RingW<1, 0>::W));
+    const int nph = ho + 9;  // phases of the segment
 
     struct Cursor {
         int r, i;
@@ -630,30 +648,9 @@ __global__ __launch_bounds__(64, 1) void k_fused_step2(const KInst *__restrict__
         else
             q.i = (q.i + 1 == ny) ? 0 : q.i + 1;
     };
-    auto load_f = [&](int ri, bool live, float f[2][9]) {
-        const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * frowb;
-        const uint32_t o16 = live ? ro + xf16 : DROP, o8 = live ? ro + xf8 : DROP;
-        float q[18];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const u32x4 v = bload4(fin, o16, (uint32_t)g * 16u * pb);
-            q[4 * g + 0] = __uint_as_float(v.x);
-            q[4 * g + 1] = __uint_as_float(v.y);
-            q[4 * g + 2] = __uint_as_float(v.z);
-            q[4 * g + 3] = __uint_as_float(v.w);
-        }
-        const u32x2 w = bload2(fin, o8, 64u * pb);
-        q[16] = __uint_as_float(w.x);
-        q[17] = __uint_as_float(w.y);
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) f[k][i] = q[9 * k + i];
-    };
     // ring row `slot` of R from a row's populations (as ring_store of the
     // single step: the same sums, the wall's densities beyond a wall)
-    auto ring_store = [&](RingW<1, 0> &R, int slot, int ri, const float q[2][9]) {
-        LDS_CHECK(slot >= 0 && slot < RR);
+    auto ring_store = [&](auto &R, int slot, int ri, const float q[2][9]) {
         const bool wall = ri < 0;
         const float da = sum9(q[0]), db = sum9(q[1]);
         const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
@@ -665,11 +662,13 @@ __global__ __launch_bounds__(64, 1) void k_fused_step2(const KInst *__restrict__
         R.dev[0][slot][cl] = da;
         R.dev[1][slot][cl] = db;
     };
-    // collision of one row of populations fa with ring R (slots sl), into S
-    auto collide_row = [&](const RingW<1, 0> &R, const int (&sl)[RR], const float (&fa)[2][9],
+    // collision of one row of populations fa with ring R (slots sl of rows
+    // c - 2 .. c + 2), into S
+    auto collide_row = [&](const auto &R, const int (&sl)[RR], const float (&fa)[2][9],
                            float (&S)[2][9]) {
+        using RT = typename std::remove_cv<typename std::remove_reference<decltype(R)>::type>::type;
         float F[2][2];
-        stencil_force(P, RingAccW<RingW<1, 0>>{R, sl, cs}, F);
+        stencil_force(P, RingAccW<RT>{R, sl, cs}, F);
         float drho[2], rho[2], jx[2], jy[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -714,138 +713,160 @@ __global__ __launch_bounds__(64, 1) void k_fused_step2(const KInst *__restrict__
         }
     };
 
-    // stage A: ring rows Y0 - 6 .. Y0 - 2, populations of rows Y0 - 4 ..
-    // Y0 - 2 in fa, fb, fc
-    int slA[RR], slB[RR];
-    Cursor crA = cursor(Y0 - 6);  // next row to load
-    float fa[2][9], fb[2][9], fc[2][9], fd[2][9];
-    {
-        float t0[2][9], t1[2][9];
-        int ri[RR];
+    if (wv == 0) {
+        // ---------------------------------------------------------- stage A
+        const __amdgpu_buffer_rsrc_t fin = make_rsrc(G.f[par], (uint32_t)ny * frowb);
+        const bool needf = L <= wo + 2 * H2 - 1;
+        const uint32_t xl = (uint32_t)wrapi(X, nx);
+        const uint32_t xf16 = needf ? xl * 16u : DROP, xf8 = needf ? xl * 8u : DROP;
+        auto load_f = [&](int ri, bool live, float f[2][9]) {
+            const uint32_t ro = (uint32_t)(ri < 0 ? 0 : ri) * frowb;
+            const uint32_t o16 = live ? ro + xf16 : DROP, o8 = live ? ro + xf8 : DROP;
+            float q[18];
 #pragma unroll
-        for (int q = 0; q < RR; ++q) {
-            ri[q] = crA.i;
-            slA[q] = q;
-            slB[q] = q;
-            advance(crA);
-        }
-        load_f(ri[0], true, t0);
-        load_f(ri[1], true, t1);
-        load_f(ri[2], true, fa);
-        load_f(ri[3], true, fb);
-        load_f(ri[4], true, fc);
-        ring_store(RA, 0, ri[0], t0);
-        ring_store(RA, 1, ri[1], t1);
-        ring_store(RA, 2, ri[2], fa);
-        ring_store(RA, 3, ri[3], fb);
-        ring_store(RA, 4, ri[4], fc);
-    }
-    wg_sync<false>();
-
-    Cursor o1c = cursor(Y0 - 5);  // output row of stage A (collided row - 1)
-    Cursor o2c = cursor(Y0 - 8);  // output row of stage B (collided row - 1), o1 - 3
-    float SA[2][9], SAp[2][9], UA[2][3], SB[2][9], SBp[2][9], UB[2][3];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) SAp[k][i] = SBp[k][i] = 0.0f;
-        UA[k][0] = UA[k][1] = UA[k][2] = 0.0f;
-        UB[k][0] = UB[k][1] = UB[k][2] = 0.0f;
-    }
-
-    // one iteration: stage A collides c1 = Y0 - 4 + it from fa and loads
-    // row c1 + 3 into fn; from it = 2 on it pulls row o1 = c1 - 1 of f(t+1)
-    // into LDS and the second ring; from it = 6 on stage B collides c2 =
-    // o1 - 2 and from it = 8 on writes row o2 = c2 - 1 of f(t+2)
-    auto iter = [&](int it, const int nit, float (&fa)[2][9], float (&fn)[2][9],
-                    float (&Sa)[2][9], float (&Sap)[2][9], float (&Sb)[2][9],
-                    float (&Sbp)[2][9]) {
-        const bool more = it + 1 < nit;
-        const int rnext = crA.i;
-        load_f(rnext, more, fn);
-        collide_row(RA, slA, fa, Sa);
-        if (it >= 2) {
-            // row o1 of f(t+1) into LDS slot o1 mod 3 and ring B
-            float g[2][9];
-            pull(o1c.r, Sap, UA, Sa, g);
-            const int fs = (it - 2) % 3;
-            FQ[fs][0][L] = make_float4(g[0][0], g[0][1], g[0][2], g[0][3]);
-            FQ[fs][1][L] = make_float4(g[0][4], g[0][5], g[0][6], g[0][7]);
-            FQ[fs][2][L] = make_float4(g[0][8], g[1][0], g[1][1], g[1][2]);
-            FQ[fs][3][L] = make_float4(g[1][3], g[1][4], g[1][5], g[1][6]);
-            FQ2[fs][L] = make_float2(g[1][7], g[1][8]);
-            // ring B: rows o1 - 4 .. o1 after the store (its oldest slot
-            // takes row o1)
-            const int freed = slB[0];
-#pragma unroll
-            for (int d = 0; d < RR - 1; ++d) slB[d] = slB[d + 1];
-            slB[RR - 1] = freed;
-            ring_store(RB, freed, o1c.i, g);
-        }
-        wg_sync<false>();
-        if (it >= 6) {
-            // stage B: collide row c2 = o1 - 2 (LDS slot (it - 4) mod 3)
-            const int fs = (it - 4) % 3;
-            float f2[2][9];
-            {
-                const float4 a = FQ[fs][0][L], b = FQ[fs][1][L], c = FQ[fs][2][L], d = FQ[fs][3][L];
-                const float2 e = FQ2[fs][L];
-                const float q[18] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x,
-                                     c.y, c.z, c.w, d.x, d.y, d.z, d.w, e.x, e.y};
-#pragma unroll
-                for (int k = 0; k < 2; ++k)
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) f2[k][i] = q[9 * k + i];
+            for (int g = 0; g < 4; ++g) {
+                const u32x4 v = bload4(fin, o16, (uint32_t)g * 16u * pb);
+                q[4 * g + 0] = __uint_as_float(v.x);
+                q[4 * g + 1] = __uint_as_float(v.y);
+                q[4 * g + 2] = __uint_as_float(v.z);
+                q[4 * g + 3] = __uint_as_float(v.w);
             }
-            int sl[RR];  // ring B slots of rows c2 - 2 .. c2 + 2 = o1 - 4 .. o1
+            const u32x2 w = bload2(fin, o8, 64u * pb);
+            q[16] = __uint_as_float(w.x);
+            q[17] = __uint_as_float(w.y);
 #pragma unroll
-            for (int d = 0; d < RR; ++d) sl[d] = slB[d];
-            collide_row(RB, sl, f2, Sb);
-            if (it >= 8) {
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[k][i] = q[9 * k + i];
+        };
+        // ring rows Y0 - 6 .. Y0 - 2, populations of rows Y0 - 4 .. Y0 - 2
+        int slA[RR];
+        Cursor cr = cursor(Y0 - 6);  // next row to load
+        float fa[2][9], fb[2][9], fc[2][9], fd[2][9];
+        {
+            float t0[2][9], t1[2][9];
+            int ri[RR];
+#pragma unroll
+            for (int q = 0; q < RR; ++q) {
+                ri[q] = cr.i;
+                slA[q] = q;
+                advance(cr);
+            }
+            load_f(ri[0], true, t0);
+            load_f(ri[1], true, t1);
+            load_f(ri[2], true, fa);
+            load_f(ri[3], true, fb);
+            load_f(ri[4], true, fc);
+            ring_store(RA, 0, ri[0], t0);
+            ring_store(RA, 1, ri[1], t1);
+            ring_store(RA, 2, ri[2], fa);
+            ring_store(RA, 3, ri[3], fb);
+            ring_store(RA, 4, ri[4], fc);
+        }
+        wg_sync<false>();  // ring A is this wavefront's alone
+        Cursor o1c = cursor(Y0 - 5);
+        float Sa[2][9], Sb[2][9], U[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Sb[k][i] = 0.0f;
+            U[k][0] = U[k][1] = U[k][2] = 0.0f;
+        }
+        auto phase = [&](int p, float (&fa)[2][9], float (&fn)[2][9], float (&S)[2][9],
+                         const float (&Sp)[2][9]) {
+            const int rnext = cr.i;
+            load_f(rnext, p <= ho + 6, fn);  // rows beyond Y0 + ho + 5 are not needed
+            collide_row(RA, slA, fa, S);
+            if (p >= 2) {
                 float g[2][9];
-                pull(o2c.r, Sbp, UB, Sb, g);
-                const uint32_t xo = (uint32_t)X;
-                const uint32_t off4 = outl ? (uint32_t)o2c.r * frowb + xo * 16u : DROP;
-                const uint32_t off2 = outl ? (uint32_t)o2c.r * frowb + xo * 8u : DROP;
-                bstore4(g[0][0], g[0][1], g[0][2], g[0][3], fout, off4, 0u);
-                bstore4(g[0][4], g[0][5], g[0][6], g[0][7], fout, off4, 16u * pb);
-                bstore4(g[0][8], g[1][0], g[1][1], g[1][2], fout, off4, 32u * pb);
-                bstore4(g[1][3], g[1][4], g[1][5], g[1][6], fout, off4, 48u * pb);
-                bstore2(g[1][7], g[1][8], fout, off2, 64u * pb);
+                pull(o1c.r, Sp, U, S, g);
+                const int fs = p & 3;
+                FQ[fs][0][L] = make_float4(g[0][0], g[0][1], g[0][2], g[0][3]);
+                FQ[fs][1][L] = make_float4(g[0][4], g[0][5], g[0][6], g[0][7]);
+                FQ[fs][2][L] = make_float4(g[0][8], g[1][0], g[1][1], g[1][2]);
+                FQ[fs][3][L] = make_float4(g[1][3], g[1][4], g[1][5], g[1][6]);
+                FQ2[fs][L] = make_float2(g[1][7], g[1][8]);
+                ring_store(RB, p % RB6, o1c.i, g);
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                UB[k][0] = Sbp[k][2];
-                UB[k][1] = Sbp[k][5];
-                UB[k][2] = Sbp[k][6];
+                U[k][0] = Sp[k][2];
+                U[k][1] = Sp[k][5];
+                U[k][2] = Sp[k][6];
             }
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            UA[k][0] = Sap[k][2];
-            UA[k][1] = Sap[k][5];
-            UA[k][2] = Sap[k][6];
-        }
-        {
             const int freed = slA[0];
 #pragma unroll
             for (int d = 0; d < RR - 1; ++d) slA[d] = slA[d + 1];
             slA[RR - 1] = freed;
             ring_store(RA, freed, rnext, fn);
-            wg_sync<false>();
-            advance(crA);
+            advance(cr);
+            advance(o1c);
+            __syncthreads();  // f(t+1) row and densities published; stage B's reads done
+        };
+        for (int p = 0; p < nph; p += 4) {
+            phase(p, fa, fd, Sa, Sb);
+            if (p + 1 < nph) phase(p + 1, fb, fa, Sb, Sa);
+            if (p + 2 < nph) phase(p + 2, fc, fb, Sa, Sb);
+            if (p + 3 < nph) phase(p + 3, fd, fc, Sb, Sa);
         }
-        advance(o1c);
-        advance(o2c);
-    };
-    const int nit = ho + 8;
-    for (int it = 0; it < nit; it += 4) {
-        iter(it, nit, fa, fd, SA, SAp, SB, SBp);
-        if (it + 1 < nit) iter(it + 1, nit, fb, fa, SAp, SA, SBp, SB);
-        if (it + 2 < nit) iter(it + 2, nit, fc, fb, SA, SAp, SB, SBp);
-        if (it + 3 < nit) iter(it + 3, nit, fd, fc, SAp, SA, SBp, SB);
+    } else {
+        // ---------------------------------------------------------- stage B
+        const __amdgpu_buffer_rsrc_t fout = make_rsrc(G.f[par ^ 1], (uint32_t)ny * frowb);
+        const bool outl = (L >= H2) && (L < wo + H2);
+        Cursor o2c = cursor(Y0 - 9);  // output row of phase p: Y0 - 9 + p
+        float Sa[2][9], Sb[2][9], U[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) Sb[k][i] = 0.0f;
+            U[k][0] = U[k][1] = U[k][2] = 0.0f;
+        }
+        auto phase = [&](int p, float (&S)[2][9], const float (&Sp)[2][9]) {
+            if (p >= 7) {
+                // collide row c2 = o1(p - 3), its populations in slot (p - 3) mod 4
+                const int fs = (p - 3) & 3;
+                float f2[2][9];
+                {
+                    const float4 a = FQ[fs][0][L], b = FQ[fs][1][L], c = FQ[fs][2][L], d = FQ[fs][3][L];
+                    const float2 e = FQ2[fs][L];
+                    const float q[18] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x,
+                                         c.y, c.z, c.w, d.x, d.y, d.z, d.w, e.x, e.y};
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) f2[k][i] = q[9 * k + i];
+                }
+                int sl[RR];  // ring slots of rows c2 - 2 .. c2 + 2 = o1(p - 5) .. o1(p - 1)
+#pragma unroll
+                for (int d = 0; d < RR; ++d) sl[d] = (p - 5 + d) % RB6;
+                collide_row(RB, sl, f2, S);
+                if (p >= 9) {
+                    float g[2][9];
+                    pull(o2c.r, Sp, U, S, g);
+                    const uint32_t xo = (uint32_t)X;
+                    const uint32_t off4 = outl ? (uint32_t)o2c.r * frowb + xo * 16u : DROP;
+                    const uint32_t off2 = outl ? (uint32_t)o2c.r * frowb + xo * 8u : DROP;
+                    bstore4(g[0][0], g[0][1], g[0][2], g[0][3], fout, off4, 0u);
+                    bstore4(g[0][4], g[0][5], g[0][6], g[0][7], fout, off4, 16u * pb);
+                    bstore4(g[0][8], g[1][0], g[1][1], g[1][2], fout, off4, 32u * pb);
+                    bstore4(g[1][3], g[1][4], g[1][5], g[1][6], fout, off4, 48u * pb);
+                    bstore2(g[1][7], g[1][8], fout, off2, 64u * pb);
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    U[k][0] = Sp[k][2];
+                    U[k][1] = Sp[k][5];
+                    U[k][2] = Sp[k][6];
+                }
+            }
+            advance(o2c);
+            __syncthreads();  // the end of the phase (stage A's next rows may now overwrite)
+        };
+        for (int p = 0; p < nph; p += 2) {
+            phase(p, Sa, Sb);
+            if (p + 1 < nph) phase(p + 1, Sb, Sa);
+        }
     }
-    wg_sync<false>();  // the next segment rewrites the rings and f(t+1) rows
     }  // segments
 }
 
@@ -1308,9 +1329,9 @@ hipError_t launch_step2(const Dev &d, int par, hipStream_t st)
 {
     if (d.nw != 1 || d.fr) return hipErrorInvalidValue;
     if (d.forcing)
-        k_fused_step2<1><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par);
+        k_fused_step2<1><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par);
     else
-        k_fused_step2<0><<<d.nwg, 64, 0, st>>>(d.insts, d.strips, d.first, par);
+        k_fused_step2<0><<<d.nwg, 128, 0, st>>>(d.insts, d.strips, d.first, par);
     return hipGetLastError();
 }
 

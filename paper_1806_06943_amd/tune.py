@@ -15,11 +15,10 @@ the smallest height whose launch has at most k workgroups per compute unit
 (a launch just past such a multiple leaves most compute units idle for its
 last round of workgroups).  Contexts whose lattice widths are all multiples
 of 64 (at most 512) also time the full-row plans (lbm_set_full_rows) at the
-same heights.  With two_step=True the two-step kernel (lbm_set_two_step:
-two time steps per launch, one-wavefront strips of at most 52 columns) is
-timed as well, at widths 52 and 48; a two-step launch counts as two steps.
-It is off by default: on this GPU it has not been faster than the single
-step on any workload measured.
+same heights.  The two-step kernel (lbm_set_two_step: two time steps per
+launch, one-wavefront strips of at most 52 columns) is timed as well, at
+widths 52 and 48 (two_step=False leaves it out); a two-step launch counts as
+two steps.
 """
 from __future__ import annotations
 
@@ -130,7 +129,7 @@ def fitted_heights(sim, width: int, ncu: int, kmax: int = FIT_KMAX, full_rows: i
 
 
 def tune(sim, candidates=CANDIDATES, nrep: int = 30, use_cache: bool = True,
-         widths=WIDTHS, balances=BALANCES, two_step: bool = False) -> dict:
+         widths=WIDTHS, balances=BALANCES, two_step: bool = True) -> dict:
     """Pick the fastest strip shape for sim's context; returns the timings."""
     arch = _arch(sim)
     key = _key(sim, arch)
