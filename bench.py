@@ -57,30 +57,23 @@ B_PER_LU = 160.0
 KERNEL_B_PER_LU = 144.0
 DOMINANT = "k_fused_step"
 
-# HBM bytes per k_fused_step launch from rocprofv3 --pmc (FETCH_SIZE x 2.0 +
+# HBM bytes per launch of the step kernel from rocprofv3 --pmc (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, factors from a 1 GiB copy of the same library), per
 # workload and strip plan (workload, width, height, workgroups per CU, full
 # rows; a trailing 2 for two steps per launch, whose bytes cover two steps),
 # valid only for the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "d2f692ed631167a0",
-                    "plans": {("batched", 0, 26, 0, 1): (128890.1 * 2.0 * 1024, 207364.7 * 1024),
-                              ("batched", 52, 64, 0, 0, 2): (123928.1 * 2.0 * 1024, 207426.3 * 1024),
-                              ("batched", 58, 64, 0, 0): (113989.5 * 2.0 * 1024, 207506.5 * 1024),
-                              ("spinodal", 52, 82, 0, 0, 2): (170264.1 * 2.0 * 1024, 295194.9 * 1024),
-                              ("spinodal", 58, 37, 0, 0): (175522.9 * 2.0 * 1024, 300329.5 * 1024),
-                              ("spinodal", 58, 40, 0, 0): (173746.1 * 2.0 * 1024, 300032.2 * 1024),
-                              ("spinodal", 58, 64, 0, 0): (163273.9 * 2.0 * 1024, 297410.8 * 1024),
-                              ("spinodal", 58, 74, 0, 0): (160226.1 * 2.0 * 1024, 295484.0 * 1024),
-                              ("spinodal", 58, 76, 0, 0): (160872.9 * 2.0 * 1024, 295563.2 * 1024),
-                              ("spinodal", 58, 78, 0, 0): (160872.2 * 2.0 * 1024, 295613.3 * 1024),
-                              ("spinodal", 58, 80, 0, 0): (159612.1 * 2.0 * 1024, 295569.2 * 1024),
-                              ("spinodal", 122, 46, 0, 0): (168301.7 * 2.0 * 1024, 296604.9 * 1024),
-                              ("spinodal", 122, 48, 0, 0): (168015.9 * 2.0 * 1024, 296574.6 * 1024),
-                              ("spinodal", 240, 37, 0, 0): (173881.7 * 2.0 * 1024, 294921.3 * 1024),
-                              ("spinodal", 240, 38, 0, 0): (173048.5 * 2.0 * 1024, 294919.4 * 1024),
-                              ("spinodal", 250, 37, 0, 0): (172514.2 * 2.0 * 1024, 295970.7 * 1024),
-                              ("spinodal", 506, 41, 0, 0): (170368.5 * 2.0 * 1024, 295190.5 * 1024),
-                              ("spinodal", 506, 42, 0, 0): (169461.7 * 2.0 * 1024, 295059.2 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "236566f2c94ed9c1",
+                    "plans": {("batched", 0, 26, 0, 1): (128896.6 * 2.0 * 1024, 207364.8 * 1024),
+                              ("batched", 52, 32, 0, 0, 2): (143555.8 * 2.0 * 1024, 208214.3 * 1024),
+                              ("batched", 52, 64, 0, 0, 2): (124032.2 * 2.0 * 1024, 207476.3 * 1024),
+                              ("batched", 58, 64, 0, 0): (113983.7 * 2.0 * 1024, 207482.4 * 1024),
+                              ("spinodal", 48, 44, 0, 0, 2): (188273.4 * 2.0 * 1024, 294913.4 * 1024),
+                              ("spinodal", 48, 90, 0, 0, 2): (169964.8 * 2.0 * 1024, 294912.8 * 1024),
+                              ("spinodal", 52, 41, 0, 0, 2): (191050.3 * 2.0 * 1024, 297178.1 * 1024),
+                              ("spinodal", 52, 47, 0, 0, 2): (184614.0 * 2.0 * 1024, 296573.6 * 1024),
+                              ("spinodal", 52, 82, 0, 0, 2): (171605.0 * 2.0 * 1024, 295626.2 * 1024),
+                              ("spinodal", 52, 108, 0, 0, 2): (165510.1 * 2.0 * 1024, 295121.6 * 1024),
+                              ("spinodal", 58, 74, 0, 0): (160258.0 * 2.0 * 1024, 295438.6 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
