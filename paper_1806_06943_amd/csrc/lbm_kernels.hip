@@ -651,14 +651,19 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
     // ring row `slot` of R from a row's populations (as ring_store of the
     // single step: the same sums, the wall's densities beyond a wall)
     auto ring_store = [&](auto &R, int slot, int ri, const float q[2][9]) {
-        const bool wall = ri < 0;
         const float da = sum9(q[0]), db = sum9(q[1]);
-        const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
-        const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + db;
+        float ra = P.rho_ref[0] + da, rb = P.rho_ref[1] + db;
+        float pa = psi_of(P, ra), pbv = psi_of(P, rb);
+        if (ri < 0) {  // a row beyond a wall (uniform): no selects on the other rows
+            ra = P.rho_wall[0];
+            rb = P.rho_wall[1];
+            pa = P.psi_wall[0];
+            pbv = P.psi_wall[1];
+        }
         R.rho[0][slot][cl] = ra;
         R.rho[1][slot][cl] = rb;
-        R.psi[0][slot][cl] = wall ? P.psi_wall[0] : psi_of(P, ra);
-        R.psi[1][slot][cl] = wall ? P.psi_wall[1] : psi_of(P, rb);
+        R.psi[0][slot][cl] = pa;
+        R.psi[1][slot][cl] = pbv;
         R.dev[0][slot][cl] = da;
         R.dev[1][slot][cl] = db;
     };
@@ -697,19 +702,35 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
     // o (Sp) and o + 1 (S): g[k][i] = f_{k,i}(x, o) after streaming
     auto pull = [&](int o, const float (&Sp)[2][9], const float (&U)[2][3], const float (&S)[2][9],
                     float (&g)[2][9]) {
-        const bool wlo = walls && o == 0;
-        const bool whi = walls && o == ny - 1;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             g[k][0] = Sp[k][0];
             g[k][1] = from_left(Sp[k][1]);
             g[k][3] = from_right(Sp[k][3]);
-            g[k][2] = wlo ? Sp[k][4] : U[k][0];
-            g[k][5] = wlo ? Sp[k][7] : from_left(U[k][1]);
-            g[k][6] = wlo ? Sp[k][8] : from_right(U[k][2]);
-            g[k][4] = whi ? Sp[k][2] : S[k][4];
-            g[k][7] = whi ? Sp[k][5] : from_right(S[k][7]);
-            g[k][8] = whi ? Sp[k][6] : from_left(S[k][8]);
+            g[k][2] = U[k][0];
+            g[k][5] = from_left(U[k][1]);
+            g[k][6] = from_right(U[k][2]);
+            g[k][4] = S[k][4];
+            g[k][7] = from_right(S[k][7]);
+            g[k][8] = from_left(S[k][8]);
+        }
+        // bounce-back next to a wall: a branch on the (uniform) row, so that
+        // rows away from walls pay no selects
+        if (walls && o == 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                g[k][2] = Sp[k][4];
+                g[k][5] = Sp[k][7];
+                g[k][6] = Sp[k][8];
+            }
+        }
+        if (walls && o == ny - 1) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                g[k][4] = Sp[k][2];
+                g[k][7] = Sp[k][5];
+                g[k][8] = Sp[k][6];
+            }
         }
     };
 
