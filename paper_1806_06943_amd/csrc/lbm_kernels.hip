@@ -354,12 +354,15 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
     // densities instead
     auto ring_store = [&](int slot, int ri, const float q[2][9]) {
         LDS_CHECK(slot >= 0 && slot < RR);
-        const bool wall = ri < 0;
         const float da = sum9(q[0]), db = sum9(q[1]);
-        const float ra = wall ? P.rho_wall[0] : P.rho_ref[0] + da;
-        const float rb = wall ? P.rho_wall[1] : P.rho_ref[1] + db;
-        const float pa = wall ? P.psi_wall[0] : psi_of(P, ra);
-        const float pbv = wall ? P.psi_wall[1] : psi_of(P, rb);
+        float ra = P.rho_ref[0] + da, rb = P.rho_ref[1] + db;
+        float pa = psi_of(P, ra), pbv = psi_of(P, rb);
+        if (ri < 0) {  // a row beyond a wall (uniform): no selects on the other rows
+            ra = P.rho_wall[0];
+            rb = P.rho_wall[1];
+            pa = P.psi_wall[0];
+            pbv = P.psi_wall[1];
+        }
         R.rho[0][slot][cl] = ra;
         R.rho[1][slot][cl] = rb;
         R.psi[0][slot][cl] = pa;
@@ -495,19 +498,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         // output row yet and write nothing
         {
             const int o = cc.r - 1;
-            const bool wlo = walls && o == 0;
-            const bool whi = walls && o == ny - 1;
             const bool st = outl && it >= 2;
             const uint32_t xo = (uint32_t)X;
             const uint32_t off4 = st ? (uint32_t)o * frowb + xo * 16u : DROP;
             const uint32_t off2 = st ? (uint32_t)o * frowb + xo * 8u : DROP;
             const uint32_t roff = st && ovr.wrho ? (uint32_t)o * rrowb + xo * 8u : DROP;
-            // component A fills planes 0, 1 and the first lane of plane 2;
-            // component B the rest of plane 2, plane 3 and the float2 plane
-            float a8 = 0.0f, ra = 0.0f;
+            float g[2][9];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                float g[9];
                 float l1 = from_left(Sprev[k][1]), l5 = from_left(Uprev[k][1]), l8 = from_left(S[k][8]);
                 float r3 = from_right(Sprev[k][3]), r6 = from_right(Uprev[k][2]), r7 = from_right(S[k][7]);
                 if constexpr (NW > 1 || FR) {
@@ -518,27 +516,43 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
                     r6 = taker ? edge[wr][0][3 * k + 1] : r6;
                     r7 = taker ? edge[wr][0][3 * k + 2] : r7;
                 }
-                g[0] = Sprev[k][0];
-                g[1] = l1;
-                g[3] = r3;
-                g[2] = wlo ? Sprev[k][4] : Uprev[k][0];
-                g[5] = wlo ? Sprev[k][7] : l5;
-                g[6] = wlo ? Sprev[k][8] : r6;
-                g[4] = whi ? Sprev[k][2] : S[k][4];
-                g[7] = whi ? Sprev[k][5] : r7;
-                g[8] = whi ? Sprev[k][6] : l8;
-                if (k == 0) {
-                    bstore4(g[0], g[1], g[2], g[3], fout, off4, 0u);
-                    bstore4(g[4], g[5], g[6], g[7], fout, off4, 16u * pb);
-                    a8 = g[8];
-                    if (ovr.wrho) ra = sum9(g);  // uniform: no sums when no densities are written
-                } else {
-                    bstore4(a8, g[0], g[1], g[2], fout, off4, 32u * pb);
-                    bstore4(g[3], g[4], g[5], g[6], fout, off4, 48u * pb);
-                    bstore2(g[7], g[8], fout, off2, 64u * pb);
-                    if (ovr.wrho) bstore2(ra, sum9(g), rout, roff, 0u);
+                g[k][0] = Sprev[k][0];
+                g[k][1] = l1;
+                g[k][3] = r3;
+                g[k][2] = Uprev[k][0];
+                g[k][5] = l5;
+                g[k][6] = r6;
+                g[k][4] = S[k][4];
+                g[k][7] = r7;
+                g[k][8] = l8;
+            }
+            // bounce-back next to a wall: a branch on the (uniform) row, so
+            // that rows away from walls pay no selects
+            if (walls && o == 0) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    g[k][2] = Sprev[k][4];
+                    g[k][5] = Sprev[k][7];
+                    g[k][6] = Sprev[k][8];
                 }
             }
+            if (walls && o == ny - 1) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    g[k][4] = Sprev[k][2];
+                    g[k][7] = Sprev[k][5];
+                    g[k][8] = Sprev[k][6];
+                }
+            }
+            // component A fills planes 0, 1 and the first lane of plane 2;
+            // component B the rest of plane 2, plane 3 and the float2 plane
+            bstore4(g[0][0], g[0][1], g[0][2], g[0][3], fout, off4, 0u);
+            bstore4(g[0][4], g[0][5], g[0][6], g[0][7], fout, off4, 16u * pb);
+            bstore4(g[0][8], g[1][0], g[1][1], g[1][2], fout, off4, 32u * pb);
+            bstore4(g[1][3], g[1][4], g[1][5], g[1][6], fout, off4, 48u * pb);
+            bstore2(g[1][7], g[1][8], fout, off2, 64u * pb);
+            // uniform: no sums when no densities are written
+            if (ovr.wrho) bstore2(sum9(g[0]), sum9(g[1]), rout, roff, 0u);
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
