@@ -609,6 +609,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
 // writes row Y0 - 9 + p of f(t+2).  Stage B never reads a slot stage A
 // writes in the same phase, and the barrier that ends a phase orders the
 // rest.
+
 // density ring of f(t+1) in the two-step kernel: six row slots of a
 // one-wavefront strip's columns
 struct RingB6 {
@@ -665,6 +666,7 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
     // ring row `slot` of R from a row's populations (as ring_store of the
     // single step: the same sums, the wall's densities beyond a wall)
     auto ring_store = [&](auto &R, int slot, int ri, const float q[2][9]) {
+        LDS_CHECK(slot >= 0 && slot < (int)(sizeof(R.rho[0]) / sizeof(R.rho[0][0])));
         const float da = sum9(q[0]), db = sum9(q[1]);
         float ra = P.rho_ref[0] + da, rb = P.rho_ref[1] + db;
         float pa = psi_of(P, ra), pbv = psi_of(P, rb);
@@ -873,7 +875,10 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
                 }
                 int sl[RR];  // ring slots of rows c2 - 2 .. c2 + 2 = o1(p - 5) .. o1(p - 1)
 #pragma unroll
-                for (int d = 0; d < RR; ++d) sl[d] = (p - 5 + d) % RB6;
+                for (int d = 0; d < RR; ++d) {
+                    sl[d] = (p - 5 + d) % RB6;
+                    LDS_CHECK(sl[d] >= 0 && sl[d] < RB6);
+                }
                 collide_row(RB, sl, f2, S);
                 if (p >= 9) {
                     float g[2][9];

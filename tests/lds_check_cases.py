@@ -1,4 +1,4 @@
-"""Strip and full-row plans of many shapes run through the checked build of the
+"""Strip, full-row and two-step plans of many shapes run through the checked build of the
 library (LDS ring and edge indices counted when out of range); prints the
 count.  Run by tests/test_gpu_lds_check.py in a child process with
 LBM_HIP_SO pointing at liblbm_hip_check.so."""
@@ -50,6 +50,21 @@ def main():
             lbm.lbm_record(sim.ctx, 0, 3, store.data_ptr())
             n = lbm.lbm_lds_checks(sim.ctx)
             print(f"full rows {spec} x {h}: {n}", flush=True)
+            total += n
+            sim.close()
+    # two steps per launch: one-wavefront strips of at most 52 columns
+    for nx, ny, walls in shapes:
+        for cols, h in ((52, 16), (48, 5), (16, 2), (52, -2)):
+            sim = lbm.Sim([inst(nx, ny, walls, nx + ny + 1)])
+            lbm.lbm_set_strip_width(sim.ctx, cols)
+            if h > 0:
+                lbm.lbm_set_tiling(sim.ctx, h)
+            else:
+                lbm.lbm_set_balance(sim.ctx, -h)
+            lbm.lbm_set_two_step(sim.ctx, 1)
+            sim.step(5)
+            n = lbm.lbm_lds_checks(sim.ctx)
+            print(f"two steps {cols} x {h} on {nx} x {ny} walls {walls}: {n}", flush=True)
             total += n
             sim.close()
     print(f"LDS_VIOLATIONS {total}", flush=True)
