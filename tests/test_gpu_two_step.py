@@ -101,6 +101,26 @@ def test_two_step_long_run_and_mode_switches(torch):
     b.close()
 
 
+def test_two_step_droplet_against_the_oracle(torch):
+    """The two-step path against the FP64 oracle directly: the 64 x 64 droplet
+    with its literal couplings after 200 steps (odd launches count: 100 two-step
+    launches), rho and u within 1e-5 norm-wise like the single step."""
+    import oracle as O
+    w = W.droplet(nx=64, ny=64, radius=12, couplings=W.COUPLINGS_LITERAL, tau=(1.0, 0.6))
+    sim = lbm.Sim([lbm.workload_instance(w)])
+    tune.apply(sim, 52, 16, 0, 0, 1)
+    sim.step(200)
+    rho, u = sim.fields()
+    p = O.Params(nx=w.nx, ny=w.ny, G_AB=w.G_AB, G1=w.G1, G2=w.G2, tau=w.tau)
+    fl = O.fields(p, O.run(p, O.init(p, w.rhoA, w.rhoB), 200))
+    rho, u = rho.cpu().numpy(), u.cpu().numpy()
+    err_rho = np.linalg.norm(rho - fl["rho"]) / np.linalg.norm(fl["rho"])
+    err_u = np.linalg.norm(u - fl["u"]) / np.linalg.norm(fl["u"])
+    say("two-step droplet vs oracle", err_rho, err_u)
+    assert err_rho < 1e-5 and err_u < 1e-5, (err_rho, err_u)
+    sim.close()
+
+
 def test_two_step_refused_plans_and_profile(torch):
     sim = lbm.Sim(instances([(128, 40, 0)]))
     lbm.lbm_set_strip_width(sim.ctx, 58)
