@@ -203,14 +203,15 @@ __device__ __forceinline__ void wg_sync()
 // wrap into range).  Memory waits are then exact.  The loads of row c + 3
 // are in flight while row c is collided.  Two barriers per row: after the
 // collision (the ring row of c - 2 and the edge values are then free /
-// published) and after the ring update.
+// published) and after the ring update; in a one-wavefront workgroup they
+// are scheduling barriers only (wg_sync).
 // FS selects the forcing: 0 the Guo term with the common velocity (Eq. 5),
 // 1 the velocity shift of the original model (momenta without F/2, BGK
 // towards the equilibrium at u^eq + tau_k F_k / rho_k, no explicit term).
 // Reads f[par]; writes f[par ^ 1] and, with ovr.wrho, rho[par ^ 1].
-// Register budget: two waves per SIMD (at most 256 VGPRs; the kernel uses
-// about 211), which every strip width meets without spilling although four
-// rows of populations are live across the collision.
+// Register budget: two waves per SIMD (at most 256 VGPRs; the instances
+// use 198-220), which every strip width meets without spilling although
+// four rows of populations are live across the collision.
 //
 // FR = 1 (full rows): for lattices whose width is a multiple of 64, a group
 // of k = nx / 64 wavefronts covers whole rows, lane l of the group's j-th
