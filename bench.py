@@ -62,19 +62,19 @@ DOMINANT = "k_fused_step"
 # workload and strip plan (workload, width, height, workgroups per CU, full
 # rows; a trailing 2 for two steps per launch, whose bytes cover two steps),
 # valid only for the kernel sources they were measured on.
-MEASURED_TRAFFIC = {"src_sha256_16": "a6bbc5ffe19fec29",
-                    "plans": {("batched", 0, 26, 0, 1): (128894.0 * 2.0 * 1024, 207365.7 * 1024),
-                              ("batched", 52, 32, 0, 0, 2): (143520.5 * 2.0 * 1024, 208065.8 * 1024),
-                              ("batched", 52, 64, 0, 0, 2): (123933.3 * 2.0 * 1024, 207451.5 * 1024),
-                              ("batched", 58, 64, 0, 0): (113986.4 * 2.0 * 1024, 207511.6 * 1024),
-                              ("spinodal", 48, 90, 0, 0, 2): (169822.1 * 2.0 * 1024, 294912.0 * 1024),
-                              ("spinodal", 52, 41, 0, 0, 2): (191753.3 * 2.0 * 1024, 296730.6 * 1024),
-                              ("spinodal", 52, 47, 0, 0, 2): (185437.0 * 2.0 * 1024, 296281.9 * 1024),
-                              ("spinodal", 52, 80, 0, 0, 2): (171552.5 * 2.0 * 1024, 295326.1 * 1024),
-                              ("spinodal", 52, 82, 0, 0, 2): (170738.0 * 2.0 * 1024, 295368.9 * 1024),
-                              ("spinodal", 52, 84, 0, 0, 2): (170549.2 * 2.0 * 1024, 295278.5 * 1024),
-                              ("spinodal", 52, 108, 0, 0, 2): (165315.9 * 2.0 * 1024, 295146.3 * 1024),
-                              ("spinodal", 58, 74, 0, 0): (160234.5 * 2.0 * 1024, 295528.1 * 1024)}}
+MEASURED_TRAFFIC = {"src_sha256_16": "105fb4621ac841a3",
+                    "plans": {("batched", 0, 26, 0, 1): (128894.1 * 2.0 * 1024, 207365.4 * 1024),
+                              ("batched", 52, 32, 0, 0, 2): (143509.4 * 2.0 * 1024, 208057.4 * 1024),
+                              ("batched", 52, 64, 0, 0, 2): (123932.4 * 2.0 * 1024, 207443.4 * 1024),
+                              ("batched", 58, 64, 0, 0): (113989.3 * 2.0 * 1024, 207506.5 * 1024),
+                              ("spinodal", 48, 90, 0, 0, 2): (170057.7 * 2.0 * 1024, 294913.0 * 1024),
+                              ("spinodal", 52, 41, 0, 0, 2): (191770.0 * 2.0 * 1024, 296757.3 * 1024),
+                              ("spinodal", 52, 47, 0, 0, 2): (185439.6 * 2.0 * 1024, 296195.6 * 1024),
+                              ("spinodal", 52, 80, 0, 0, 2): (171588.7 * 2.0 * 1024, 295292.2 * 1024),
+                              ("spinodal", 52, 82, 0, 0, 2): (171005.8 * 2.0 * 1024, 295664.1 * 1024),
+                              ("spinodal", 52, 84, 0, 0, 2): (170543.8 * 2.0 * 1024, 295228.6 * 1024),
+                              ("spinodal", 52, 108, 0, 0, 2): (165318.0 * 2.0 * 1024, 295133.0 * 1024),
+                              ("spinodal", 58, 74, 0, 0): (160236.9 * 2.0 * 1024, 295506.5 * 1024)}}
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
@@ -256,12 +256,19 @@ def bench_adjoint(torch, lbm, W, steps, window):
     fwd.step(200)
     ms_fwd = timed(torch, fwd.stream, lambda: fwd.step(steps))
     fwd.close()
+    # the gradient's forward pass records every state, one step per launch:
+    # its contexts take the best single-step plan
+    grad_tuning = tuning
+    if tuning.get("two_step", 0):
+        one = lbm.Sim([inst], device="cuda:0")
+        grad_tuning = tune.tune(one, use_cache=False, two_step=False)
+        one.close()
     prob = AD.Problem(inst, steps=steps, objective="dp", window=window)
     window_used = prob.window
     store_gb = prob.state_bytes() * min(window_used, steps) * (1 if window_used >= steps else 2) / 1e9
     for s in (prob.sim, prob.rec):  # forward context and window re-run context
-        tune.apply(s, tuning["width"], tuning["best"], tuning.get("balance", 0),
-                   tuning.get("full_rows", 0), tuning.get("two_step", 0))
+        tune.apply(s, grad_tuning["width"], grad_tuning["best"], grad_tuning.get("balance", 0),
+                   grad_tuning.get("full_rows", 0), 0)
     prob.value_and_grad()  # warm-up: allocations, graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -293,6 +300,8 @@ def bench_adjoint(torch, lbm, W, steps, window):
             "objective": "J_dp (smooth pressure jump)",
             "strip_plan": {k: tuning.get(k) for k in ("width", "best", "balance", "full_rows",
                                                       "two_step")},
+            "gradient_strip_plan": {k: grad_tuning.get(k) for k in ("width", "best", "balance",
+                                                                    "full_rows")},
             "plain_fwd_mlups": round(pf, 1),
             "fwd_adjoint_mlups": round(fa, 1), "ratio_to_plain_fwd": round(fa / pf, 4),
             "J": J, "grad_theta": {n: float(v) for n, v in zip(lbm.THETA_NAMES, g)},
