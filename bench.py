@@ -461,6 +461,10 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE)",
                      "algorithmic_bytes": spl * B_PER_LU * N, "steps_per_launch": spl,
                      "kernel": kname, "bytes_per_lu": B_PER_LU,
+                     # what bounds the kernel as measured by its counters: one step
+                     # per launch streams at the copy rate; two steps per launch
+                     # move half the bytes and are bound by VALU issue
+                     "limiter": "hbm" if spl == 1 else "valu issue (HBM moved: counted_gbps)",
                      "kernel_bytes_per_lu": KERNEL_B_PER_LU / spl,
                      "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / spl / B_PER_LU, 1),
                      "counted_gbps": None if traffic is None else
