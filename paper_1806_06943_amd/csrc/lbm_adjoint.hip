@@ -179,16 +179,27 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_density(AdjPar A, const float 
     }
 }
 
-// Stage rho and psi of both components over the tile and its halo of 2
-// (periodic in x, periodic in y or the wall densities beyond a wall).
+// The local transpose takes tiles of 64 x LTY nodes, each thread LSUB
+// nodes of one column: a lattice of 512 x 512 then gives every lane of the
+// GPU two nodes in one round of blocks, where one node per thread would
+// leave a second, thinly occupied round (its 168 registers allow three
+// wavefronts per SIMD, 1.33 rounds of 64 x 4 tiles there), and the staged
+// halo rows are shared by more nodes.
+constexpr int LSUB = 2;
+constexpr int LTY = TY * LSUB;
+
+// Stage rho and psi of both components over a tile of H rows and its halo
+// of 2 (periodic in x, periodic in y or the wall densities beyond a wall).
+template <int H>
 struct RTile {
-    float rho[2][AH][AW];
-    float psi[2][AH][AW];
+    float rho[2][H + 2 * HALO][AW];
+    float psi[2][H + 2 * HALO][AW];
 };
 
-__device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile &T)
+template <int H>
+__device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile<H> &T)
 {
-    for (int t = threadIdx.x; t < AW * AH; t += NTHREADS) {
+    for (int t = threadIdx.x; t < AW * (H + 2 * HALO); t += NTHREADS) {
         const int lx = t % AW, ly = t / AW;
         const int gx = wrapi(x0 + lx - HALO, A.nx);
         int gy = y0 + ly - HALO;
@@ -213,22 +224,24 @@ __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile
 // MODE 0: adjoint step.  MODE 1: seed of J_Q = (1/nx) sum_x u_x.
 // Block partials: [0..4] theta, [5] J.
 template <int MODE>
-// three wavefronts per SIMD: 168 VGPRs (the populations and the stencil sums
-// are not held across the transpose), LDS 33 KB per block
-__global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float *__restrict__ f,
+// two wavefronts per SIMD (the populations and the stencil sums are not
+// held across the transpose), LDS 38 KB per block
+__global__ __launch_bounds__(NTHREADS, 2) void k_adj_local(AdjPar A, const float *__restrict__ f,
                                                         const float *__restrict__ lam_next,
                                                         float *__restrict__ lam)
 {
-    __shared__ RTile T;
+    __shared__ RTile<LTY> T;
     // each thread's FP64 stencil sums [k][s1x s1y s2x s2y srx sry], parked in
     // LDS between the force recompute and the own-node terms
     __shared__ double SS[NTHREADS][2][6];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * LTY;
     stage_rho(A, x0, y0, T);
     __syncthreads();
-    const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
-    const int x = x0 + lx, y = y0 + ly;
     double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int sub = 0; sub < LSUB; ++sub) {
+    const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX) + TY * sub;
+    const int x = x0 + lx, y = y0 + ly;
     if (x < A.nx && y < A.ny) {
         const int cx = lx + HALO, cy = ly + HALO;
         float rho[2], psi[2], drho[2], mx[2], my[2], F[2][2];
@@ -275,7 +288,8 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
         // Compiler-only barrier (no instruction): the populations (from
         // cache) and the stencil sums (from LDS) are read again below instead
         // of being held in registers across the FP64 transpose, which keeps
-        // the kernel within the register budget of two wavefronts per SIMD.
+        // the kernel within the register budget of two wavefronts per SIMD
+        // without spilling.
         asm volatile("" ::: "memory");
 
         // The transpose is evaluated in FP64 from the FP32 linearisation point:
@@ -359,7 +373,7 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
             const R rt = (R)rho[0] + rho[1];
             const R irt = 1.0 / rt;
             const R ubar = ((R)jx[0] + jx[1]) * irt;
-            acc[5] = ubar * (R)A.qscale;
+            acc[5] += ubar * (R)A.qscale;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 // q (e_x - u_x) / rho
@@ -394,6 +408,7 @@ __global__ __launch_bounds__(NTHREADS, 3) void k_adj_local(AdjPar A, const float
             acc[3 + k] += gtau[k];
         }
     }
+    }  // sub
     // adjoint steps add into their block's slot (cleared by k_adj_zero before a
     // run; launches on one stream are ordered, so no two blocks share a slot)
     block_sum(acc, A.part + (int64_t)block_id() * NPART, MODE == 0);
@@ -611,6 +626,10 @@ __global__ __launch_bounds__(256) void k_adj_final(AdjPar A, int nblocks, double
 
 dim3 agrid(const AdjPar &A) { return dim3((A.nx + TX - 1) / TX, (A.ny + TY - 1) / TY); }
 int nblk(const AdjPar &A) { return (int)(((A.nx + TX - 1) / TX) * ((A.ny + TY - 1) / TY)); }
+// grid of the local transpose (tiles of LTY rows; its partial slots are the
+// first lblk of the nblk)
+dim3 lgrid(const AdjPar &A) { return dim3((A.nx + TX - 1) / TX, (A.ny + LTY - 1) / LTY); }
+int lblk(const AdjPar &A) { return (int)(((A.nx + TX - 1) / TX) * ((A.ny + LTY - 1) / LTY)); }
 
 }  // namespace
 
@@ -648,7 +667,7 @@ hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rde
         LAUNCH_CHECK();
         B.rdev = A.rscr;
     }
-    k_adj_local<0><<<agrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
+    k_adj_local<0><<<lgrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
     LAUNCH_CHECK();
     k_adj_force<<<agrid(B), NTHREADS, 0, st>>>(B);
     LAUNCH_CHECK();
@@ -681,7 +700,7 @@ hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, fl
     if (which == 0) {
         k_obj_dp_sums<<<agrid(A), NTHREADS, 0, st>>>(A);
     } else if (which == 1) {
-        k_adj_local<1><<<agrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
+        k_adj_local<1><<<lgrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
         LAUNCH_CHECK();
         k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
         LAUNCH_CHECK();
@@ -690,7 +709,8 @@ hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, fl
         k_obj_lin<<<agrid(A), NTHREADS, 0, st>>>(A, f, lam, which);
     }
     LAUNCH_CHECK();
-    k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), nullptr);
+    // the local transpose writes the partials of its own (fewer) blocks
+    k_adj_final<<<1, 256, 0, st>>>(A, which == 1 ? lblk(A) : nblk(A), nullptr);
     LAUNCH_CHECK();
     return hipSuccess;
 }
@@ -718,7 +738,7 @@ hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const f
     switch (j) {
     case 0: k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f); break;
     // (the timed local pass accumulates into its partial slots; cleared before use)
-    case 1: k_adj_local<0><<<agrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
+    case 1: k_adj_local<0><<<lgrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
     case 2: k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A); break;
     default: k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad); break;
     }
