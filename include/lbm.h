@@ -330,7 +330,9 @@ int lbm_record(lbm_ctx *ctx, int32_t inst, int64_t nsteps, float *f_store_dev);
  * are buffers of one population state in the lbm_get_populations layout
  * (18*nx*ny floats); neither may overlap the store or each other.
  * grad_dev[0..4] (device FP64, may be NULL) += the theta-gradient of the
- * window, reduced once in a fixed order.  Asynchronous. */
+ * window, reduced once in a fixed order.  The result equals nsteps calls of
+ * lbm_adjoint_step bit for bit in lam (one launch per step: each step also
+ * transposes the force stencils of the step after it).  Asynchronous. */
 int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_store_dev,
                     float *lam_dev, float *tmp_dev, double *grad_dev);
 

@@ -29,9 +29,15 @@
 //                  kept as one pending value per node and component, which
 //                  the next step's gather (or k_adj_combine) adds;
 // followed by a fixed-order FP64 reduction of the per-block theta partials.
+// Within a run of steps the force pass is folded into the next step's local
+// pass: that pass stages psi Fbar and rho Fbar of the step before around its
+// tile and forms the pending addition where its gather reads it (the same
+// operations, so the same bits), one launch per step instead of two.
 // Scratch (densities, Fbar, block partials, the pending additions) lives in
 // the instance's field planes of the workspace.
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "lbm_internal.h"
 
@@ -135,6 +141,65 @@ __device__ __forceinline__ void sum9s(const V &v, T c1, T c2, T &sx, T &sy)
     sy = c1 * d01 + c2 * (d11 + dm11);
 }
 
+// The pending addition of component k at one node: the neighbour terms of
+// the transposed force stencils, psibar_k exp(-rho_k / rho0) + rhobar_k, from
+// q(kk, d, dx, dy) = psi_kk Fbar_kk,d and r(kk, d, dx, dy) = rho_kk Fbar_kk,d
+// of the node displaced by (dx, dy); rk is the node's own density.  With
+//   psibar_k(y) = sum_e c_k(e) e . (q_k(y + e) - q_k(y - e))   (e over half of D2Q25,
+//                 c_k(e) = G1_k w(e) + G2_k p(e))
+//   rhobar_k(y) = G_AB sum_e w(e) e . (r_kb(y + e) - r_kb(y - e))   (half of D2Q9)
+template <class QA, class RA>
+__device__ __forceinline__ float force_add(const AdjPar &A, int k, const QA &q, const RA &r,
+                                           float rk)
+{
+    float ax, ay, bx, by, cx_, cy_, dx_, dy_;
+    auto qx = [&](int dx, int dy) { return q(k, 0, dx, dy); };
+    auto qy = [&](int dx, int dy) { return q(k, 1, dx, dy); };
+    const float c1 = A.G1[k] * W1 + A.G2[k] * P1, c2 = A.G1[k] * W2 + A.G2[k] * P2;
+    const float c4 = A.G2[k] * P4, c5 = A.G2[k] * P5, c8 = A.G2[k] * P8;
+    sum25<float>(qx, c1, c2, c4, c5, c8, ax, ay);  // uses the x component along e_x, e_y
+    sum25<float>(qy, c1, c2, c4, c5, c8, bx, by);
+    const float psibar = ax + by;  // e . q summed: e_x q_x + e_y q_y
+    // inter-species: r of the other component
+    auto rx = [&](int dx, int dy) { return r(1 - k, 0, dx, dy); };
+    auto ry = [&](int dx, int dy) { return r(1 - k, 1, dx, dy); };
+    sum9s<float>(rx, W1, W2, cx_, cy_);
+    sum9s<float>(ry, W1, W2, dx_, dy_);
+    (void)ay;
+    (void)bx;
+    (void)cy_;
+    (void)dx_;
+    return psibar * expf(-rk * A.inv_rho0) + A.gab * (cx_ + dy_);
+}
+
+// psi Fbar and rho Fbar of the force adjoints in planes fb (state densities
+// rdev) over a tile of W x H staged nodes whose first node is lattice node
+// (x0, y0) (periodic wrap; zero beyond a wall, where no force acts)
+template <int W, int H>
+__device__ __forceinline__ void stage_qr(const AdjPar &A, const float *__restrict__ rdev, int fb,
+                                         int x0, int y0, float (&q)[2][2][H][W],
+                                         float (&r)[2][2][H][W])
+{
+    for (int t = threadIdx.x; t < W * H; t += NTHREADS) {
+        const int lx = t % W, ly = t / W;
+        const int gx = wrapi(x0 + lx, A.nx);
+        const int gy = y0 + ly;
+        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);  // no force acts there
+        const int yy = ghost ? 0 : wrapi(gy, A.ny);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float rk = A.rho_ref[k] + rdev[didx(A, k, gx, yy)];
+            const float p = apsi(A, rk);
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const float fbv = ghost ? 0.0f : A.scr[sidx(A, fb + 2 * k + d, gx, yy)];
+                q[k][d][ly][lx] = p * fbv;
+                r[k][d][ly][lx] = rk * fbv;
+            }
+        }
+    }
+}
+
 // Sum of NV doubles over the block (256 threads = 4 wavefronts) in a fixed
 // order; thread 0 writes out[0..NV).
 template <int NV>
@@ -223,19 +288,58 @@ __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile
 // ---------------------------------------------------------------- local transpose
 // MODE 0: adjoint step.  MODE 1: seed of J_Q = (1/nx) sum_x u_x.
 // Block partials: [0..4] theta, [5] J.
-template <int MODE>
+// The folded force pass of the step before: psi Fbar and rho Fbar staged
+// with a halo of FH = 3 (the gather reads the addition one node beyond the
+// tile, whose stencil reaches two nodes further), and the addition itself
+// over the tile and a halo of 1.
+constexpr int FH = 3;
+struct FoldTile {
+    float q[2][2][LTY + 2 * FH][TX + 2 * FH];
+    float r[2][2][LTY + 2 * FH][TX + 2 * FH];
+    float add[2][LTY + 2][TX + 2];
+};
+
+// FOLD 1 (MODE 0 only): the gather adds the pending addition of the step
+// before formed here from its force adjoints (planes A.fbi, densities
+// A.rdev_next); FOLD 0: read from scratch (SCR_ADD, written by k_adj_force
+// or cleared).
+template <int MODE, int FOLD>
 // two wavefronts per SIMD (the populations and the stencil sums are not
-// held across the transpose), LDS 38 KB per block
+// held across the transpose), LDS 38 KB per block (73 KB folded)
 __global__ __launch_bounds__(NTHREADS, 2) void k_adj_local(AdjPar A, const float *__restrict__ f,
                                                         const float *__restrict__ lam_next,
                                                         float *__restrict__ lam)
 {
+    static_assert(MODE == 0 || !FOLD, "the seed has no step before");
     __shared__ RTile<LTY> T;
     // each thread's FP64 stencil sums [k][s1x s1y s2x s2y srx sry], parked in
     // LDS between the force recompute and the own-node terms
     __shared__ double SS[NTHREADS][2][6];
+    __shared__ typename std::conditional<FOLD != 0, FoldTile, char>::type FT;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * LTY;
     stage_rho(A, x0, y0, T);
+    if constexpr (FOLD != 0) {
+        stage_qr<TX + 2 * FH, LTY + 2 * FH>(A, A.rdev_next, A.fbi, x0 - FH, y0 - FH, FT.q, FT.r);
+        __syncthreads();
+        // the addition at the tile's nodes and one node around (rows beyond a
+        // wall are never gathered: bounce-back reads the node itself)
+        for (int t = threadIdx.x; t < (TX + 2) * (LTY + 2); t += NTHREADS) {
+            const int ax = t % (TX + 2), ay = t / (TX + 2);
+            const int gx = wrapi(x0 + ax - 1, A.nx), gy = y0 + ay - 1;
+            if (A.walls && (gy < 0 || gy >= A.ny)) {
+                FT.add[0][ay][ax] = FT.add[1][ay][ax] = 0.0f;
+                continue;
+            }
+            const int yy = wrapi(gy, A.ny);
+            const int qx = ax + FH - 1, qy = ay + FH - 1;  // the node in the staged tile
+            auto q = [&](int k, int d, int dx, int dy) { return FT.q[k][d][qy + dy][qx + dx]; };
+            auto r = [&](int k, int d, int dx, int dy) { return FT.r[k][d][qy + dy][qx + dx]; };
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                FT.add[k][ay][ax] =
+                    force_add(A, k, q, r, A.rho_ref[k] + A.rdev_next[didx(A, k, gx, yy)]);
+        }
+    }
     __syncthreads();
     double acc[NPART] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
@@ -315,9 +419,14 @@ __global__ __launch_bounds__(NTHREADS, 2) void k_adj_local(AdjPar A, const float
                 const int ys = bounce ? y : wrap1(yd, A.ny);
                 const int is = bounce ? c_op[i] : i;
 #pragma unroll
-                for (int k = 0; k < 2; ++k)
-                    a[k][i] = lam_next[xidx(A, k * 9 + is, xs, ys)] +
-                              A.scr[sidx(A, SCR_ADD + k, xs, ys)];
+                for (int k = 0; k < 2; ++k) {
+                    float add;
+                    if constexpr (FOLD != 0)
+                        add = FT.add[k][ly + 1 + (bounce ? 0 : c_ey[i])][lx + 1 + (bounce ? 0 : c_ex[i])];
+                    else
+                        add = A.scr[sidx(A, SCR_ADD + k, xs, ys)];
+                    a[k][i] = lam_next[xidx(A, k * 9 + is, xs, ys)] + add;
+                }
             }
             // transpose of Eq. 1 (BGK + Guo) at fixed rho_k, u, F_k
             R ubx = 0.0, uby = 0.0, rbar[2];
@@ -400,8 +509,8 @@ __global__ __launch_bounds__(NTHREADS, 2) void k_adj_local(AdjPar A, const float
             for (int i = 0; i < 9; ++i)
                 lam[xidx(A, k * 9 + i, x, y)] =
                     (float)((lam_a[k] * (R)a[k][i] + emul(c_ex[i], mbx[k]) + emul(c_ey[i], mby[k]) + lam_c[k]) + rown);
-            A.scr[sidx(A, SCR_FBAR + 2 * k, x, y)] = (float)Fb[k][0];
-            A.scr[sidx(A, SCR_FBAR + 2 * k + 1, x, y)] = (float)Fb[k][1];
+            A.scr[sidx(A, A.fbo + 2 * k, x, y)] = (float)Fb[k][0];
+            A.scr[sidx(A, A.fbo + 2 * k + 1, x, y)] = (float)Fb[k][1];
             acc[0] += -(R)psi[k] * s1F;
             acc[1] += -(R)psi[k] * s2F;
             acc[2] += -(R)rho[k] * srF;
@@ -422,11 +531,8 @@ __global__ __launch_bounds__(256) void k_adj_zero(AdjPar A, int n)
 }
 
 // ---------------------------------------------------------------- force transpose
-// Neighbour terms: with q_k = psi_k Fbar_k and r_k = rho_k Fbar_k,
-//   psibar_k(y) = sum_e c_k(e) e . (q_k(y + e) - q_k(y - e))   (e over half of D2Q25,
-//                 c_k(e) = G1_k w(e) + G2_k p(e))
-//   rhobar_kb(y) += G_AB sum_e w(e) e . (r_k(y + e) - r_k(y - e))   (half of D2Q9)
-// and lam_{k,i}(y) += psibar_k(y) exp(-rho_k / rho0) + rhobar_k(y), the same for
+// Neighbour terms (force_add): with q_k = psi_k Fbar_k and r_k = rho_k Fbar_k,
+// lam_{k,i}(y) += psibar_k(y) exp(-rho_k / rho0) + rhobar_k(y), the same for
 // all i: the kernel writes that addition per component (SCR_ADD), and the
 // next step's gather, or the combine pass, adds it where lam is read.
 struct QTile {
@@ -438,52 +544,18 @@ __global__ __launch_bounds__(NTHREADS) void k_adj_force(AdjPar A)
 {
     __shared__ QTile T;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    for (int t = threadIdx.x; t < AW * AH; t += NTHREADS) {
-        const int lx = t % AW, ly = t / AW;
-        const int gx = wrapi(x0 + lx - HALO, A.nx);
-        const int gy = y0 + ly - HALO;
-        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);  // no force acts there
-        const int yy = ghost ? 0 : wrapi(gy, A.ny);
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float r = A.rho_ref[k] + A.rdev[didx(A, k, gx, yy)];
-            const float p = apsi(A, r);
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const float fb = ghost ? 0.0f : A.scr[sidx(A, SCR_FBAR + 2 * k + d, gx, yy)];
-                T.q[k][d][ly][lx] = p * fb;
-                T.r[k][d][ly][lx] = r * fb;
-            }
-        }
-    }
+    stage_qr<AW, AH>(A, A.rdev, A.fbo, x0 - HALO, y0 - HALO, T.q, T.r);
     __syncthreads();
     const int lx = (int)(threadIdx.x % TX), ly = (int)(threadIdx.x / TX);
     const int x = x0 + lx, y = y0 + ly;
     if (x >= A.nx || y >= A.ny) return;
     const int cx = lx + HALO, cy = ly + HALO;
+    auto q = [&](int k, int d, int dx, int dy) { return T.q[k][d][cy + dy][cx + dx]; };
+    auto r = [&](int k, int d, int dx, int dy) { return T.r[k][d][cy + dy][cx + dx]; };
     float add[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        float ax, ay, bx, by, cx_, cy_, dx_, dy_;
-        auto qx = [&](int dx, int dy) { return T.q[k][0][cy + dy][cx + dx]; };
-        auto qy = [&](int dx, int dy) { return T.q[k][1][cy + dy][cx + dx]; };
-        const float c1 = A.G1[k] * W1 + A.G2[k] * P1, c2 = A.G1[k] * W2 + A.G2[k] * P2;
-        const float c4 = A.G2[k] * P4, c5 = A.G2[k] * P5, c8 = A.G2[k] * P8;
-        sum25<float>(qx, c1, c2, c4, c5, c8, ax, ay);  // uses the x component along e_x, e_y
-        sum25<float>(qy, c1, c2, c4, c5, c8, bx, by);
-        const float psibar = ax + by;  // e . q summed: e_x q_x + e_y q_y
-        // inter-species: r of the other component
-        auto rx = [&](int dx, int dy) { return T.r[1 - k][0][cy + dy][cx + dx]; };
-        auto ry = [&](int dx, int dy) { return T.r[1 - k][1][cy + dy][cx + dx]; };
-        sum9s<float>(rx, W1, W2, cx_, cy_);
-        sum9s<float>(ry, W1, W2, dx_, dy_);
-        const float r = A.rho_ref[k] + A.rdev[didx(A, k, x, y)];
-        add[k] = psibar * expf(-r * A.inv_rho0) + A.gab * (cx_ + dy_);
-        (void)ay;
-        (void)bx;
-        (void)cy_;
-        (void)dx_;
-    }
+    for (int k = 0; k < 2; ++k)
+        add[k] = force_add(A, k, q, r, A.rho_ref[k] + A.rdev[didx(A, k, x, y)]);
 #pragma unroll
     for (int k = 0; k < 2; ++k) A.scr[sidx(A, SCR_ADD + k, x, y)] = add[k];
 }
@@ -667,13 +739,31 @@ hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rde
         LAUNCH_CHECK();
         B.rdev = A.rscr;
     }
-    k_adj_local<0><<<lgrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
+    k_adj_local<0, 0><<<lgrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
     LAUNCH_CHECK();
     k_adj_force<<<agrid(B), NTHREADS, 0, st>>>(B);
     LAUNCH_CHECK();
     return hipSuccess;
 }
 
+
+hipError_t launch_adjoint_local(const AdjPar &A, bool fold, const float *f, const float *lam_next,
+                                float *lam, hipStream_t st)
+{
+    if (fold)
+        k_adj_local<0, 1><<<lgrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam);
+    else
+        k_adj_local<0, 0><<<lgrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_force(const AdjPar &A, hipStream_t st)
+{
+    k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
+    LAUNCH_CHECK();
+    return hipSuccess;
+}
 
 hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st)
 {
@@ -700,7 +790,7 @@ hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, fl
     if (which == 0) {
         k_obj_dp_sums<<<agrid(A), NTHREADS, 0, st>>>(A);
     } else if (which == 1) {
-        k_adj_local<1><<<lgrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
+        k_adj_local<1, 0><<<lgrid(A), NTHREADS, 0, st>>>(A, f, nullptr, lam);
         LAUNCH_CHECK();
         k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A);
         LAUNCH_CHECK();
@@ -728,8 +818,9 @@ int adjoint_blocks(int nx, int ny) { return ((nx + TX - 1) / TX) * ((ny + TY - 1
 
 const char *adjoint_kernel_name(int j)
 {
-    static const char *names[] = {"k_adj_density", "k_adj_local", "k_adj_force", "k_adj_final"};
-    return j >= 0 && j < 4 ? names[j] : "";
+    static const char *names[] = {"k_adj_density", "k_adj_local", "k_adj_force", "k_adj_final",
+                                  "k_adj_local_fold"};
+    return j >= 0 && j < N_ADJ_KERNELS ? names[j] : "";
 }
 
 hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const float *lam_next,
@@ -738,9 +829,19 @@ hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const f
     switch (j) {
     case 0: k_adj_density<<<agrid(A), NTHREADS, 0, st>>>(A, f); break;
     // (the timed local pass accumulates into its partial slots; cleared before use)
-    case 1: k_adj_local<0><<<lgrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
+    case 1: k_adj_local<0, 0><<<lgrid(A), NTHREADS, 0, st>>>(A, f, lam_next, lam); break;
     case 2: k_adj_force<<<agrid(A), NTHREADS, 0, st>>>(A); break;
-    default: k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad); break;
+    case 3: k_adj_final<<<1, 256, 0, st>>>(A, nblk(A), grad); break;
+    // the local pass of a run's later steps, with the force pass of the step
+    // before folded in (here: the force adjoints in the second set of planes
+    // and the same state's densities, for timing)
+    default: {
+        AdjPar B = A;
+        B.fbi = A.fbo == SCR_FBAR ? SCR_FBAR2 : SCR_FBAR;
+        B.rdev_next = A.rdev;
+        k_adj_local<0, 1><<<lgrid(B), NTHREADS, 0, st>>>(B, f, lam_next, lam);
+        break;
+    }
     }
     LAUNCH_CHECK();
     return hipSuccess;

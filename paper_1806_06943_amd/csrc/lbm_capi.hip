@@ -1055,6 +1055,9 @@ static AdjPar adj_par(const lbm_ctx *ctx, int inst)
     A.scr = K.fld;
     A.rscr = K.fld + (int64_t)SCR_RDEV * K.plane;  // one packed density buffer <= 2 planes
     A.rdev = A.rscr;
+    A.fbo = SCR_FBAR;
+    A.fbi = SCR_FBAR2;
+    A.rdev_next = nullptr;
     A.part = (double *)(K.fld + (int64_t)SCR_PART * K.plane);
     A.res = A.part + (int64_t)adjoint_blocks(p.nx, p.ny) * NPART;
     return A;
@@ -1185,11 +1188,30 @@ int lbm_adjoint_run(lbm_ctx *ctx, int32_t inst, int64_t nsteps, const float *f_s
     if (nsteps == 0) return LBM_OK;
     const AdjPar A = adj_par(ctx, inst);
     hipStream_t st = ctx->stream;
-    hipError_t e = launch_adjoint_zero(A, st);
+    hipError_t e = launch_adjoint_zero(A, st);  // also: no pending addition before the first step
     float *cur = lam_dev, *nxt = tmp_dev;
+    // Step j writes its force adjoints to one of two plane sets (by the
+    // parity of j); every step after the first forms the pending addition of
+    // the step before from that step's set and state (the force pass folded
+    // into its local pass), so only the last step runs the force pass.
+    auto fb_set = [](int64_t j) { return (j & 1) ? SCR_FBAR2 : SCR_FBAR; };
     for (int64_t j = nsteps - 1; j >= 0 && e == hipSuccess; --j) {
-        e = launch_adjoint_body(A, f_store_dev + j * S, f_store_dev + j * S + L.fsize, cur, nxt, st);
+        AdjPar B = A;
+        B.rdev = f_store_dev + j * S + L.fsize;
+        B.fbo = fb_set(j);
+        const bool fold = j < nsteps - 1;
+        if (fold) {
+            B.fbi = fb_set(j + 1);
+            B.rdev_next = f_store_dev + (j + 1) * S + L.fsize;
+        }
+        e = launch_adjoint_local(B, fold, f_store_dev + j * S, cur, nxt, st);
         std::swap(cur, nxt);
+    }
+    if (e == hipSuccess) {
+        AdjPar B = A;
+        B.rdev = f_store_dev + L.fsize;  // state 0
+        B.fbo = fb_set(0);
+        e = launch_adjoint_force(B, st);
     }
     if (e == hipSuccess) e = launch_adjoint_final(A, grad_dev, st);
     // the last step's pending addition, into lam_dev

@@ -48,8 +48,9 @@ constexpr int SW = 64;                  // lanes of a one-wavefront strip
 constexpr int SWO = SW - 2 - 2 * HALO;  // output columns of a full one-wavefront strip
 constexpr int RR = 2 * HALO + 1;        // density-ring rows
 
-// number of FP32 planes in the per-instance field scratch
-constexpr int NFLD = 9;
+// number of FP32 planes in the per-instance field scratch (the observables
+// use the first nine, the adjoint passes all)
+constexpr int NFLD = 13;
 enum FieldPlane { FLD_RHOA = 0, FLD_RHOB, FLD_UX, FLD_UY, FLD_PB, FLD_MX, FLD_MY, FLD_JX, FLD_JY };
 
 // Launch parameters of one instance (device copy lives in the workspace).

@@ -76,12 +76,16 @@ hipError_t lds_checks(unsigned int *bad, hipStream_t st);
 // density deviations (the first 2 planes, holding one packed density buffer),
 // force adjoints [k][d] (4), then FP64 block partials
 // (NPART per 64 x 4 tile, a small part of one plane) followed by NPART final
-// sums, and the force transpose's addition to every lam_{k,i} of a node (2).
+// sums, the force transpose's addition to every lam_{k,i} of a node (2), and
+// a second set of force adjoints (4): the steps of a run alternate between
+// the two sets, each reading the one the step before wrote.
 constexpr int SCR_RDEV = 0;
 constexpr int SCR_FBAR = 2;
 constexpr int SCR_PART = 6;
 constexpr int SCR_ADD = 7;
+constexpr int SCR_FBAR2 = 9;
 constexpr int NPART = 8;
+static_assert(SCR_FBAR2 + 4 <= NFLD, "adjoint scratch planes");
 
 // Parameters of one instance for the adjoint kernels (passed by value).
 struct AdjPar {
@@ -98,6 +102,9 @@ struct AdjPar {
     float *scr;             // scratch planes
     float *rscr;            // density deviations written by k_adj_density (packed, rho[y][x][k])
     const float *rdev;      // density deviations of the state being transposed (packed)
+    int fbo;                // first of the 4 planes the local pass writes its force adjoints to
+    int fbi;                // (folded runs) the planes the step before wrote its force adjoints to
+    const float *rdev_next; // (folded runs) density deviations of the state after this one
     double *part;           // [blocks][NPART]
     double *res;            // [NPART]
 };
@@ -115,13 +122,21 @@ hipError_t launch_adjoint_zero(const AdjPar &A, hipStream_t st);
 hipError_t launch_adjoint_body(const AdjPar &A, const float *f, const float *rdev,
                                const float *lam_next, float *lam, hipStream_t st);
 hipError_t launch_adjoint_combine(const AdjPar &A, const float *in, float *out, hipStream_t st);
+// The two passes of a step of a run, separately.  The local pass with fold
+// forms the pending addition of the step before (force adjoints in planes
+// A.fbi, densities A.rdev_next) itself where its gather reads it, instead of
+// a force pass of the step before writing it; the force pass reads planes
+// A.fbo and writes the pending addition.
+hipError_t launch_adjoint_local(const AdjPar &A, bool fold, const float *f, const float *lam_next,
+                                float *lam, hipStream_t st);
+hipError_t launch_adjoint_force(const AdjPar &A, hipStream_t st);
 hipError_t launch_adjoint_final(const AdjPar &A, double *grad, hipStream_t st);
 hipError_t launch_objective_pass1(const AdjPar &A, int which, const float *f, float *lam,
                                   hipStream_t st);
 hipError_t launch_objective_dp_seed(const AdjPar &A, float *lam, double mA, double mB, double SA,
                                     double SB, hipStream_t st);
 int adjoint_blocks(int nx, int ny);
-constexpr int N_ADJ_KERNELS = 4;
+constexpr int N_ADJ_KERNELS = 5;
 const char *adjoint_kernel_name(int j);
 hipError_t launch_adjoint_kernel(const AdjPar &A, int j, const float *f, const float *lam_next,
                                  float *lam, double *grad, hipStream_t st);

@@ -173,6 +173,40 @@ def test_run_gradient_matches_fp64_run(torch, which):
     prob.close()
 
 
+@pytest.mark.parametrize("walls", [0, 1])
+def test_run_equals_single_steps(torch, walls):
+    """A run of adjoint steps forms each step's pending force-transpose addition
+    inside the next step's local pass (from the force adjoints of the step
+    before); single adjoint steps run the force pass and fold the addition into
+    lam at once.  lam(0) must agree bit for bit, the gradient to FP64 rounding
+    (the run sums its per-block partials over all steps before the final sum)."""
+    say("run vs single steps", walls)
+    d = droplet_instance(48, 40, walls, R=10, g=1e-5)
+    n = 30
+    prob = AD.Problem(d, steps=n, objective="dp", window=n)
+    J, g, lam0 = prob.value_and_grad()
+    prob.close()
+    sim = lbm.Sim([d])
+    states = [sim.populations()]
+    for _ in range(n):
+        sim.step(1)
+        states.append(sim.populations())
+    lam = torch.empty_like(states[-1])
+    Js, direct = sim.adjoint_seed("dp", states[-1], lam)
+    grad = torch.zeros(5, dtype=torch.float64, device="cuda")
+    nxt = torch.empty_like(lam)
+    for t in range(n - 1, -1, -1):
+        sim.adjoint_step(states[t], lam, nxt, grad)
+        lam, nxt = nxt, lam
+    torch.cuda.synchronize()
+    gs = grad.cpu().numpy() + direct
+    say("J", J, Js, "grad", g, gs)
+    assert J == Js
+    assert torch.equal(lam0, lam)
+    assert np.abs(g - gs).max() <= 1e-10 * np.abs(gs).max(), (g, gs)
+    sim.close()
+
+
 def test_conserved_objectives_have_zero_gradient(torch):
     say("zero gradients")
     d = droplet_instance(64, 64, 0, R=16, g=0.0)
