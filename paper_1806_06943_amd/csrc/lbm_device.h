@@ -329,8 +329,12 @@ __device__ __forceinline__ void common_velocity(const Par &P, const float rho[2]
 // drho: their correctly rounded sum, rho: density, F: force, (ux, uy): u^eq.
 // Opposite directions share e.u and e.F: the equilibrium splits into the
 // even part 4.5 (e.u)^2 - 1.5 u.u and the odd part 3 e.u, the Guo bracket
-// into 9 (e.u)(e.F) - 3 u.F and 3 e.F.
-template <class Par>
+// into 9 (e.u)(e.F) - 3 u.F and 3 e.F.  GUO = false drops the Guo term (the
+// velocity shift, whose force enters through u^eq; F is then ignored).
+// e.u and e.F are formed from the lattice vectors' components directly
+// (u_x, u_y, u_x + u_y, u_y - u_x): a product with a zero component would
+// still be evaluated (it is not an exact zero for every input).
+template <bool GUO = true, class Par>
 __device__ __forceinline__ void collide(const Par &P, int k, const float f[9], float drho,
                                         float rho, float Fx, float Fy, float ux, float uy,
                                         float out[9])
@@ -341,31 +345,35 @@ __device__ __forceinline__ void collide(const Par &P, int k, const float f[9], f
     const float omit = 1.0f - it;
     const float cf = P.cf[k];
     const float uu = fmaf(ux, ux, uy * uy);
-    const float uF = fmaf(ux, Fx, uy * Fy);
+    const float uF = GUO ? fmaf(ux, Fx, uy * Fy) : 0.0f;
     // relaxation of the small part g = f - c a towards f^eq - c a, plus C
     auto relax = [&](float fi, float c, float feq_small, float C) {
         const float rest = c * a;
         const float g = fi - rest;
-        return rest + fmaf(g, omit, fmaf(feq_small, it, C));
+        return rest + fmaf(g, omit, GUO ? fmaf(feq_small, it, C) : feq_small * it);
     };
     // rest direction: e = 0
     out[0] = relax(f[0], 16.0f, 16.0f * (r36 * (-1.5f * uu)), 16.0f * (cf * (-3.0f * uF)));
-    // pairs (i, opp(i)) with e_i = (ex, ey) and weight c
-    auto pair = [&](int i, int j, float ex, float ey, float c) {
-        const float eu = fmaf(ex, ux, ey * uy);
-        const float eF = fmaf(ex, Fx, ey * Fy);
+    // pairs (i, opp(i)) with weight c, e_i . u = eu and e_i . F = eF
+    auto pair = [&](int i, int j, float eu, float eF, float c) {
         const float qe = fmaf(4.5f * eu, eu, -1.5f * uu);
         const float qo = 3.0f * eu;
-        const float ce = fmaf(9.0f * eu, eF, -3.0f * uF);
-        const float co = 3.0f * eF;
-        const float rc = c * r36, fc = c * cf;
-        out[i] = relax(f[i], c, rc * (qe + qo), fc * (ce + co));
-        out[j] = relax(f[j], c, rc * (qe - qo), fc * (ce - co));
+        const float rc = c * r36;
+        if constexpr (GUO) {
+            const float ce = fmaf(9.0f * eu, eF, -3.0f * uF);
+            const float co = 3.0f * eF;
+            const float fc = c * cf;
+            out[i] = relax(f[i], c, rc * (qe + qo), fc * (ce + co));
+            out[j] = relax(f[j], c, rc * (qe - qo), fc * (ce - co));
+        } else {
+            out[i] = relax(f[i], c, rc * (qe + qo), 0.0f);
+            out[j] = relax(f[j], c, rc * (qe - qo), 0.0f);
+        }
     };
-    pair(1, 3, 1.0f, 0.0f, 4.0f);
-    pair(2, 4, 0.0f, 1.0f, 4.0f);
-    pair(5, 7, 1.0f, 1.0f, 1.0f);
-    pair(6, 8, -1.0f, 1.0f, 1.0f);
+    pair(1, 3, ux, Fx, 4.0f);                 // e = (1, 0)
+    pair(2, 4, uy, Fy, 4.0f);                 // e = (0, 1)
+    pair(5, 7, ux + uy, Fx + Fy, 1.0f);       // e = (1, 1)
+    pair(6, 8, uy - ux, Fy - Fx, 1.0f);       // e = (-1, 1)
 }
 
 }  // namespace lbm

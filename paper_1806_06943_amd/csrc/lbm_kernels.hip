@@ -453,8 +453,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
                 if constexpr (FS) {
                     // equilibrium velocity shifted by tau_k F_k / rho_k
                     const float s = recip(rho[k] * P.it[k]);
-                    collide(P, k, fa[k], drho[k], rho[k], 0.0f, 0.0f, fmaf(F[k][0], s, ux),
-                            fmaf(F[k][1], s, uy), S[k]);
+                    collide<false>(P, k, fa[k], drho[k], rho[k], 0.0f, 0.0f,
+                                   fmaf(F[k][0], s, ux), fmaf(F[k][1], s, uy), S[k]);
                 } else {
                     collide(P, k, fa[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
                 }
@@ -707,8 +707,8 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
         for (int k = 0; k < 2; ++k) {
             if constexpr (FS) {
                 const float s = recip(rho[k] * P.it[k]);
-                collide(P, k, fa[k], drho[k], rho[k], 0.0f, 0.0f, fmaf(F[k][0], s, ux),
-                        fmaf(F[k][1], s, uy), S[k]);
+                collide<false>(P, k, fa[k], drho[k], rho[k], 0.0f, 0.0f,
+                               fmaf(F[k][0], s, ux), fmaf(F[k][1], s, uy), S[k]);
             } else {
                 collide(P, k, fa[k], drho[k], rho[k], F[k][0], F[k][1], ux, uy, S[k]);
             }
