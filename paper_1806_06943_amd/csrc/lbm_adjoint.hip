@@ -11,7 +11,8 @@
 // read in the library's packed layout: a recorded window's slots, or the
 // instance's spare buffer into which the entry points import a caller's
 // state.  lam is the caller's, in the export layout [2][9][ny][nx].  One
-// adjoint step is up to three passes over 64 x 4 tiles:
+// adjoint step is up to three passes over 2-D tiles (64 x 4 nodes; 64 x 8,
+// two nodes per thread, for the local transpose):
 //   k_adj_density  density deviations of f (rounded as the forward step's)
 //                  into scratch (a recorded state brings the densities the
 //                  step wrote, bitwise the same);
@@ -29,10 +30,12 @@
 //                  kept as one pending value per node and component, which
 //                  the next step's gather (or k_adj_combine) adds;
 // followed by a fixed-order FP64 reduction of the per-block theta partials.
-// Within a run of steps the force pass is folded into the next step's local
-// pass: that pass stages psi Fbar and rho Fbar of the step before around its
-// tile and forms the pending addition where its gather reads it (the same
-// operations, so the same bits), one launch per step instead of two.
+// Within a run of steps (swept from the last time step back) the force pass
+// of step j + 1 is folded into the local pass of step j: that pass stages
+// psi Fbar and rho Fbar of step j + 1 around its tile and forms the pending
+// addition where its gather reads it (the same operations, so the same
+// bits), one launch per step instead of two.  "The step before" below is
+// the step the sweep processed before, j + 1.
 // Scratch (densities, Fbar, block partials, the pending additions) lives in
 // the instance's field planes of the workspace.
 #include <stdint.h>
