@@ -353,8 +353,12 @@ int lbm_set_params(lbm_ctx *ctx, int32_t inst, const lbm_params *params);
 
 /* Time the kernels of one adjoint step of instance inst like
  * lbm_profile_step (nrep launches of each kernel between HIP events on the
- * context's stream).  lam_out_dev and grad_dev are overwritten with
- * meaningless values.  Synchronises the stream. */
+ * context's stream): the density pass, the local transpose, the force
+ * transpose, the final sums, and the local transpose with the force
+ * transpose of the step before folded in (the kernel of an adjoint run's
+ * later steps).  ms[j] and names[j] for j < min(max_k, *n_kernels).
+ * lam_out_dev and grad_dev are overwritten with meaningless values.
+ * Synchronises the stream. */
 int lbm_profile_adjoint(lbm_ctx *ctx, int32_t inst, const float *f_dev, const float *lam_in_dev,
                         float *lam_out_dev, double *grad_dev, int32_t nrep, int32_t max_k,
                         double *ms, const char **names, int32_t *n_kernels);
