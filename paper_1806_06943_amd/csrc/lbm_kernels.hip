@@ -611,14 +611,41 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
 // writes in the same phase, and the barrier that ends a phase orders the
 // rest.
 
-// density ring of f(t+1) in the two-step kernel: six row slots of a
-// one-wavefront strip's columns
-struct RingB6 {
-    static constexpr int NS = 6;
+// Density ring of the two-step kernel: NS row slots of a one-wavefront
+// strip's columns (column j: lattice column X0 - 6 + j).  A slot holds one
+// row of the three fields with the two components side by side, so that all
+// reads of a row by one lane's stencil lie within 2 KiB after the first:
+// one address register per slot and immediate offsets, with no address
+// arithmetic per read.
+template <int NS_>
+struct RingP {
+    static constexpr int NS = NS_;
     static constexpr int W = RingW<1, 0>::W;
-    float rho[2][NS][W];
-    float psi[2][NS][W];
-    float dev[2][NS][W];
+    struct Row {
+        float2 psi[W];
+        float2 rho[W];
+        float2 dev[W];  // density deviations (own-node term of the collision)
+    };
+    Row row[NS];
+};
+
+// accessor into a packed ring: slot[dy + 2] is the slot of lattice row
+// c + dy, cb the ring column of the stencil's left edge (centre - HALO)
+template <class RT>
+struct RingAccP {
+    const RT &R;
+    const int *slot;
+    int cb;
+    __device__ float psi(int k, int dx, int dy) const
+    {
+        const float2 v = R.row[slot[dy + HALO]].psi[cb + HALO + dx];
+        return k ? v.y : v.x;
+    }
+    __device__ float rho(int k, int dx, int dy) const
+    {
+        const float2 v = R.row[slot[dy + HALO]].rho[cb + HALO + dx];
+        return k ? v.y : v.x;
+    }
 };
 
 template <int FS>
@@ -626,9 +653,9 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
                                                         const int4 *__restrict__ segs,
                                                         const int *__restrict__ first, int par)
 {
-    constexpr int RB6 = RingB6::NS;
-    __shared__ RingW<1, 0> RA;        // densities of f(t): stage A only
-    __shared__ RingB6 RB;             // densities of f(t+1)
+    constexpr int RB6 = 6;
+    __shared__ RingP<RR> RA;          // densities of f(t): stage A only
+    __shared__ RingP<RB6> RB;         // densities of f(t+1)
     __shared__ float4 FQ[4][4][64];   // f(t+1) rows: four float4 planes per slot
     __shared__ float2 FQ2[4][64];     // and the float2 plane
     const int L = (int)threadIdx.x & 63;
@@ -646,8 +673,11 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
     constexpr int H2 = 2 * (HALO + 1);  // columns left of the output for the two stages
     const int X = X0 - H2 + L;
     const int cl = L;                        // ring column of this lane
-    const int cs = cl < HALO ? HALO : cl;    // stencil centre (never left of the ring)
-    LDS_CHECK((cs + HALO < RingW<1, 0>::W));
+    // left edge of the stencil (never left of the ring): the lane's centre
+    // is cb + HALO, which differs from cl only on lanes 0 and 1, whose
+    // collisions no output uses
+    const int cb = cl < HALO ? 0 : cl - HALO;
+    LDS_CHECK((cb + 2 * HALO < RingP<RR>::W));
     const int nph = ho + 9;  // phases of the segment
 
     struct Cursor {
@@ -667,7 +697,7 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
     // ring row `slot` of R from a row's populations (as ring_store of the
     // single step: the same sums, the wall's densities beyond a wall)
     auto ring_store = [&](auto &R, int slot, int ri, const float q[2][9]) {
-        LDS_CHECK(slot >= 0 && slot < (int)(sizeof(R.rho[0]) / sizeof(R.rho[0][0])));
+        LDS_CHECK(slot >= 0 && slot < R.NS);
         const float da = sum9(q[0]), db = sum9(q[1]);
         float ra = P.rho_ref[0] + da, rb = P.rho_ref[1] + db;
         float pa = psi_of(P, ra), pbv = psi_of(P, rb);
@@ -677,12 +707,9 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
             pa = P.psi_wall[0];
             pbv = P.psi_wall[1];
         }
-        R.rho[0][slot][cl] = ra;
-        R.rho[1][slot][cl] = rb;
-        R.psi[0][slot][cl] = pa;
-        R.psi[1][slot][cl] = pbv;
-        R.dev[0][slot][cl] = da;
-        R.dev[1][slot][cl] = db;
+        R.row[slot].rho[cl] = make_float2(ra, rb);
+        R.row[slot].psi[cl] = make_float2(pa, pbv);
+        R.row[slot].dev[cl] = make_float2(da, db);
     };
     // collision of one row of populations fa with ring R (slots sl of rows
     // c - 2 .. c + 2), into S
@@ -690,12 +717,11 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
                            float (&S)[2][9]) {
         using RT = typename std::remove_cv<typename std::remove_reference<decltype(R)>::type>::type;
         float F[2][2];
-        stencil_force(P, RingAccW<RT>{R, sl, cs}, F);
-        float drho[2], rho[2], jx[2], jy[2];
+        stencil_force(P, RingAccP<RT>{R, sl, cb}, F);
+        const float2 dv = R.row[sl[HALO]].dev[cb + HALO], rv = R.row[sl[HALO]].rho[cb + HALO];
+        float drho[2] = {dv.x, dv.y}, rho[2] = {rv.x, rv.y}, jx[2], jy[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            drho[k] = R.dev[k][sl[HALO]][cl];
-            rho[k] = R.rho[k][sl[HALO]][cl];
             float mx, my;
             mom9(fa[k], mx, my);
             jx[k] = FS ? mx : fmaf(0.5f, F[k][0], mx);
@@ -859,6 +885,12 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
             for (int i = 0; i < 9; ++i) Sb[k][i] = 0.0f;
             U[k][0] = U[k][1] = U[k][2] = 0.0f;
         }
+        // slB[d]: ring slot of row o1(p - 5 + d), i.e. (p - 5 + d) mod 6,
+        // rotated by one each phase (as stage A's slots, so that the compiler
+        // can carry each slot's LDS address from phase to phase)
+        int slB[RB6];
+#pragma unroll
+        for (int d = 0; d < RB6; ++d) slB[d] = (d + 1) % RB6;
         auto phase = [&](int p, float (&S)[2][9], const float (&Sp)[2][9]) {
             if (p >= 7) {
                 // collide row c2 = o1(p - 3), its populations in slot (p - 3) mod 4
@@ -877,8 +909,8 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
                 int sl[RR];  // ring slots of rows c2 - 2 .. c2 + 2 = o1(p - 5) .. o1(p - 1)
 #pragma unroll
                 for (int d = 0; d < RR; ++d) {
-                    sl[d] = (p - 5 + d) % RB6;
-                    LDS_CHECK(sl[d] >= 0 && sl[d] < RB6);
+                    sl[d] = slB[d];
+                    LDS_CHECK(sl[d] == (p - 5 + d) % RB6);
                 }
                 collide_row(RB, sl, f2, S);
                 if (p >= 9) {
@@ -900,6 +932,10 @@ __global__ __launch_bounds__(128, 2) void k_fused_step2(const KInst *__restrict_
                     U[k][2] = Sp[k][6];
                 }
             }
+            const int oldest = slB[0];
+#pragma unroll
+            for (int d = 0; d < RB6 - 1; ++d) slB[d] = slB[d + 1];
+            slB[RB6 - 1] = oldest;
             advance(o2c);
             __syncthreads();  // the end of the phase (stage A's next rows may now overwrite)
         };
