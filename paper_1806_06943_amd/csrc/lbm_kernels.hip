@@ -124,12 +124,18 @@ __device__ __forceinline__ float from_right(float v)
 // mode (FR) the group of wavefronts that starts at wavefront w0 owns the
 // 68 w0 ... columns: lattice column X at 68 w0 + HALO + X, with the HALO
 // columns on either side holding the periodic wrap of the row.
+// A slot holds one row of the three fields with the two components side by
+// side: the stencil reads of a row are immediate offsets from one address
+// per slot.
 template <int NW, int FR>
 struct RingW {
     static constexpr int W = FR ? 68 * NW : 64 * NW + 2 * HALO;
-    float rho[2][RR][W];
-    float psi[2][RR][W];
-    float dev[2][RR][W];  // density deviations (own-node term of the collision)
+    struct Row {
+        float2 psi[W];
+        float2 rho[W];
+        float2 dev[W];  // density deviations (own-node term of the collision)
+    };
+    Row row[RR];
 };
 
 // Index checks of the LDS ring and edge arrays, compiled in with
@@ -155,8 +161,16 @@ struct RingAccW {
     const RT &R;
     const int *slot;
     int cx;
-    __device__ float psi(int k, int dx, int dy) const { return R.psi[k][slot[dy + HALO]][cx + dx]; }
-    __device__ float rho(int k, int dx, int dy) const { return R.rho[k][slot[dy + HALO]][cx + dx]; }
+    __device__ float psi(int k, int dx, int dy) const
+    {
+        const float2 v = R.row[slot[dy + HALO]].psi[cx + dx];
+        return k ? v.y : v.x;
+    }
+    __device__ float rho(int k, int dx, int dy) const
+    {
+        const float2 v = R.row[slot[dy + HALO]].rho[cx + dx];
+        return k ? v.y : v.x;
+    }
 };
 
 // Barrier of a fused-step workgroup.  A one-wavefront workgroup needs none:
@@ -364,18 +378,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
             pa = P.psi_wall[0];
             pbv = P.psi_wall[1];
         }
-        R.rho[0][slot][cl] = ra;
-        R.rho[1][slot][cl] = rb;
-        R.psi[0][slot][cl] = pa;
-        R.psi[1][slot][cl] = pbv;
-        R.dev[0][slot][cl] = da;
-        R.dev[1][slot][cl] = db;
+        R.row[slot].rho[cl] = make_float2(ra, rb);
+        R.row[slot].psi[cl] = make_float2(pa, pbv);
+        R.row[slot].dev[cl] = make_float2(da, db);
         if constexpr (FR) {
             if (cw >= 0) {  // the row's periodic wrap (stencil values only)
-                R.rho[0][slot][cw] = ra;
-                R.rho[1][slot][cw] = rb;
-                R.psi[0][slot][cw] = pa;
-                R.psi[1][slot][cw] = pbv;
+                R.row[slot].rho[cw] = make_float2(ra, rb);
+                R.row[slot].psi[cw] = make_float2(pa, pbv);
             }
         }
     };
@@ -436,11 +445,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_fused_step(
         {
             float F[2][2];
             stencil_force(P, RingAccW<RingW<NW, FR>>{R, slot, cs}, F);
-            float drho[2], rho[2], jx[2], jy[2];
+            // the node's own terms (at the stencil centre: the same column
+            // except on the two load-only lanes, whose collision is unused)
+            const float2 dv = R.row[slot[HALO]].dev[cs], rv = R.row[slot[HALO]].rho[cs];
+            float drho[2] = {dv.x, dv.y}, rho[2] = {rv.x, rv.y}, jx[2], jy[2];
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                drho[k] = R.dev[k][slot[HALO]][cl];
-                rho[k] = R.rho[k][slot[HALO]][cl];
                 float mx, my;
                 mom9(fa[k], mx, my);
                 jx[k] = FS ? mx : fmaf(0.5f, F[k][0], mx);
