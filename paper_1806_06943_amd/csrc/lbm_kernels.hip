@@ -105,17 +105,16 @@ __device__ __forceinline__ void bstore4(float a, float b, float c, float d,
 }
 
 // Lane shifts of a wavefront through DPP (lane l receives lane l - 1, resp.
-// l + 1; the end lanes keep their own value and are never consumed).
+// l + 1; the end lanes, which no output consumes, receive 0: with the
+// bound control set the shift needs no copy of its source to keep)
 __device__ __forceinline__ float from_left(float v)
 {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 __device__ __forceinline__ float from_right(float v)
 {
-    return __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // Density ring of a strip of NW wavefronts: RR rows (a rolling window over
