@@ -75,20 +75,39 @@ MEASURED_TRAFFIC = {"src_sha256_16": "ea6c0bc489be7912",
                               ("spinodal", 52, 84, 0, 0, 2): (170378.0 * 2.0 * 1024, 295360.9 * 1024),
                               ("spinodal", 52, 108, 0, 0, 2): (165365.1 * 2.0 * 1024, 295152.9 * 1024),
                               ("spinodal", 58, 74, 0, 0): (160223.2 * 2.0 * 1024, 295694.9 * 1024)}}
+# VALU instructions per launch of the step kernel from rocprofv3 --pmc
+# SQ_INSTS_VALU (wave64 instructions summed over the chip; the count repeats
+# exactly from launch to launch), keyed and valid like MEASURED_TRAFFIC.
+MEASURED_VALU = {"src_sha256_16": "ea6c0bc489be7912",
+                 "plans": {("batched", 0, 26, 0, 1): 24454488,
+                           ("batched", 52, 32, 0, 0, 2): 67153440,
+                           ("batched", 52, 64, 0, 0, 2): 61395360,
+                           ("batched", 58, 64, 0, 0): 29361360,
+                           ("spinodal", 48, 90, 0, 0, 2): 85653535,
+                           ("spinodal", 52, 41, 0, 0, 2): 86133200,
+                           ("spinodal", 52, 47, 0, 0, 2): 84697392,
+                           ("spinodal", 52, 80, 0, 0, 2): 80391488,
+                           ("spinodal", 52, 82, 0, 0, 2): 80161640,
+                           ("spinodal", 52, 84, 0, 0, 2): 80161640,
+                           ("spinodal", 52, 108, 0, 0, 2): 78726592,
+                           ("spinodal", 58, 74, 0, 0): 35013540}}
+# VALU issue peak: 256 CUs x 4 SIMDs, each SIMD 16 lanes wide, so one wave64
+# VALU instruction per SIMD every 4 cycles at 2.4 GHz: 614.4 G instructions
+# per second (78.6 TFLOP/s of FP32 FMA; the build leaves packed FP32 out).
+VALU_ISSUE_PEAK = 256 * 4 * 2.4 / 4
 KERNEL_SOURCES = ("paper_1806_06943_amd/csrc/lbm_device.h",
                   "paper_1806_06943_amd/csrc/lbm_kernels.hip")
 
 
-def measured_traffic(lbm, sim, workload):
-    """Counter-based bytes per launch under sim's current strip plan, or None
-    once the kernel or the plan differs from the measured ones."""
+def _measured(lbm, sim, workload, table):
+    """The table's entry for sim's current strip plan, or None once the kernel
+    sources or the plan differ from the measured ones."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    t = MEASURED_TRAFFIC
-    if h.hexdigest()[:16] != t["src_sha256_16"]:
+    if h.hexdigest()[:16] != table["src_sha256_16"]:
         return None
     fr = lbm.lbm_get_full_rows(sim.ctx)
     bal = lbm.lbm_get_balance(sim.ctx)
@@ -96,8 +115,25 @@ def measured_traffic(lbm, sim, workload):
            0 if bal else lbm.lbm_get_tiling(sim.ctx), bal, fr)
     if lbm.lbm_get_two_step(sim.ctx):
         key = key + (2,)
-    plan = t["plans"].get(key)
+    return table["plans"].get(key)
+
+
+def measured_traffic(lbm, sim, workload):
+    """Counter-based bytes per launch under sim's current strip plan, or None."""
+    plan = _measured(lbm, sim, workload, MEASURED_TRAFFIC)
     return None if plan is None else round(plan[0] + plan[1])
+
+
+def valu_roofline(insts, k_ms):
+    """VALU issue rate of a launch of `insts` counted instructions lasting k_ms
+    against VALU_ISSUE_PEAK, or None without a count."""
+    if insts is None:
+        return None
+    rate = insts / (k_ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(rate, 1), "peak": VALU_ISSUE_PEAK,
+            "unit": "G wave64 VALU instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4),
+            "valu_insts_per_launch": insts,
+            "source": "rocprofv3 --pmc SQ_INSTS_VALU per dispatch, same kernel sources and plan"}
 
 
 def parse():
@@ -183,6 +219,8 @@ def bench_batched(torch, lbm, tune, W, steps):
     k_ms = ms / steps
     k_iso = tune.step_ms(sim, 50)
     traffic = measured_traffic(lbm, sim, "batched")
+    spl = 2 if lbm.lbm_get_two_step(sim.ctx) else 1
+    valu = valu_roofline(_measured(lbm, sim, "batched", MEASURED_VALU), spl * k_ms)
     lap = None
     gold = golden_batched_laplace() if steps == BATCHED_ORACLE_STEPS else None
     if gold is not None and len(gold) == len(ws):
@@ -204,6 +242,7 @@ def bench_batched(torch, lbm, tune, W, steps):
            "traffic": traffic,
            "traffic_b_per_lu": None if traffic is None else
            round(traffic / nodes / (2 if lbm.lbm_get_two_step(sim.ctx) else 1), 1),
+           "valu": valu,
            "laplace_error": lap,
            "all_finite": all(o["finite"] for o in obs)}
     sim.close()
@@ -442,6 +481,7 @@ def main():
 
     cpu = None if a.no_cpu else cpu_baseline(w, steps=a.cpu_steps)
     traffic = measured_traffic(lbm, sim, "spinodal")
+    valu = valu_roofline(_measured(lbm, sim, "spinodal", MEASURED_VALU), k_ms)
 
     mass_drift = [abs(obs1[0]["mass"][k] - obs0[0]["mass"][k]) / obs0[0]["mass"][k] for k in range(2)]
     out = {
@@ -474,7 +514,10 @@ def main():
                      "counted_gbps": None if traffic is None else
                      round(traffic / (k_ms * 1e-3) / 1e9, 1),
                      "kernel_ms": round(k_ms, 5),
-                     "kernel_ms_isolated": round(prof[kname], 5)},
+                     "kernel_ms_isolated": round(prof[kname], 5),
+                     # the same launches against the VALU issue peak (the
+                     # two-step kernel's limiter)
+                     "valu": valu},
         "kernels_ms": {k: round(v, 5) for k, v in prof.items()},
         "alg_gbps_whole_step": round(mlups * 1e6 * B_PER_LU / 1e9, 1),
         "copy_kernel_gbps": round(copy_gbps, 1),
