@@ -242,6 +242,9 @@ def bench_batched(torch, lbm, tune, W, steps):
            "traffic": traffic,
            "traffic_b_per_lu": None if traffic is None else
            round(traffic / nodes / (2 if lbm.lbm_get_two_step(sim.ctx) else 1), 1),
+           "counted_gbps": None if traffic is None else round(traffic / (spl * k_ms * 1e-3) / 1e9, 1),
+           "counted_frac": None if traffic is None else
+           round(traffic / (spl * k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
            "valu": valu,
            "laplace_error": lap,
            "all_finite": all(o["finite"] for o in obs)}
@@ -513,6 +516,9 @@ def main():
                      "achieved_at_kernel_bytes": round(achieved * KERNEL_B_PER_LU / spl / B_PER_LU, 1),
                      "counted_gbps": None if traffic is None else
                      round(traffic / (k_ms * 1e-3) / 1e9, 1),
+                     # % HBM peak from the counted DRAM-side bytes
+                     "counted_frac": None if traffic is None else
+                     round(traffic / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                      "kernel_ms": round(k_ms, 5),
                      "kernel_ms_isolated": round(prof[kname], 5),
                      # the same launches against the VALU issue peak (the
