@@ -175,6 +175,14 @@ __device__ __forceinline__ float force_add(const AdjPar &A, int k, const QA &q, 
     return psibar * expf(-rk * A.inv_rho0) + A.gab * (cx_ + dy_);
 }
 
+// The staging loops below issue every global load of a thread's share of
+// the tile before the first use: loads under a per-element branch (the
+// rows beyond a wall) would each wait for their data before the next is
+// issued.  An element past the tile, or in a row beyond a wall, loads a
+// valid node (row 0, the last element) whose value goes unused.
+template <int N>
+constexpr int stage_iters() { return (N + NTHREADS - 1) / NTHREADS; }
+
 // psi Fbar and rho Fbar of the force adjoints in planes fb (state densities
 // rdev) over a tile of W x H staged nodes whose first node is lattice node
 // (x0, y0) (periodic wrap; zero beyond a wall, where no force acts)
@@ -183,19 +191,37 @@ __device__ __forceinline__ void stage_qr(const AdjPar &A, const float *__restric
                                          int x0, int y0, float (&q)[2][2][H][W],
                                          float (&r)[2][2][H][W])
 {
-    for (int t = threadIdx.x; t < W * H; t += NTHREADS) {
+    constexpr int N = W * H, IT = stage_iters<N>();
+    float rv[IT][2], fv[IT][2][2];
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int t = min((int)threadIdx.x + j * NTHREADS, N - 1);
         const int lx = t % W, ly = t / W;
         const int gx = wrapi(x0 + lx, A.nx);
         const int gy = y0 + ly;
-        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);  // no force acts there
+        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);
         const int yy = ghost ? 0 : wrapi(gy, A.ny);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const float rk = A.rho_ref[k] + rdev[didx(A, k, gx, yy)];
+            rv[j][k] = rdev[didx(A, k, gx, yy)];
+#pragma unroll
+            for (int d = 0; d < 2; ++d) fv[j][k][d] = A.scr[sidx(A, fb + 2 * k + d, gx, yy)];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int t = (int)threadIdx.x + j * NTHREADS;
+        if (t >= N) break;
+        const int lx = t % W, ly = t / W;
+        const int gy = y0 + ly;
+        const bool ghost = A.walls && (gy < 0 || gy >= A.ny);  // no force acts there
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float rk = A.rho_ref[k] + rv[j][k];
             const float p = apsi(A, rk);
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                const float fbv = ghost ? 0.0f : A.scr[sidx(A, fb + 2 * k + d, gx, yy)];
+                const float fbv = ghost ? 0.0f : fv[j][k][d];
                 q[k][d][ly][lx] = p * fbv;
                 r[k][d][ly][lx] = rk * fbv;
             }
@@ -267,10 +293,24 @@ struct RTile {
 template <int H>
 __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile<H> &T)
 {
-    for (int t = threadIdx.x; t < AW * (H + 2 * HALO); t += NTHREADS) {
+    constexpr int N = AW * (H + 2 * HALO), IT = stage_iters<N>();
+    float dv[IT][2];
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int t = min((int)threadIdx.x + j * NTHREADS, N - 1);
         const int lx = t % AW, ly = t / AW;
         const int gx = wrapi(x0 + lx - HALO, A.nx);
-        int gy = y0 + ly - HALO;
+        const int gy = y0 + ly - HALO;
+        const int yy = (A.walls && (gy < 0 || gy >= A.ny)) ? 0 : wrapi(gy, A.ny);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) dv[j][k] = A.rdev[didx(A, k, gx, yy)];
+    }
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+        const int t = (int)threadIdx.x + j * NTHREADS;
+        if (t >= N) break;
+        const int lx = t % AW, ly = t / AW;
+        const int gy = y0 + ly - HALO;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             float r, p;
@@ -278,8 +318,7 @@ __device__ __forceinline__ void stage_rho(const AdjPar &A, int x0, int y0, RTile
                 r = A.rho_wall[k];
                 p = A.psi_wall[k];
             } else {
-                const int yy = wrapi(gy, A.ny);
-                r = A.rho_ref[k] + A.rdev[didx(A, k, gx, yy)];
+                r = A.rho_ref[k] + dv[j][k];
                 p = apsi(A, r);
             }
             T.rho[k][ly][lx] = r;
@@ -325,22 +364,35 @@ __global__ __launch_bounds__(NTHREADS, 2) void k_adj_local(AdjPar A, const float
         stage_qr<TX + 2 * FH, LTY + 2 * FH>(A, A.rdev_next, A.fbi, x0 - FH, y0 - FH, FT.q, FT.r);
         __syncthreads();
         // the addition at the tile's nodes and one node around (rows beyond a
-        // wall are never gathered: bounce-back reads the node itself)
-        for (int t = threadIdx.x; t < (TX + 2) * (LTY + 2); t += NTHREADS) {
+        // wall are never gathered: bounce-back reads the node itself); the
+        // densities are loaded first, as in the staging loops
+        constexpr int NA = (TX + 2) * (LTY + 2), IA = stage_iters<NA>();
+        float rn[IA][2];
+#pragma unroll
+        for (int j = 0; j < IA; ++j) {
+            const int t = min((int)threadIdx.x + j * NTHREADS, NA - 1);
             const int ax = t % (TX + 2), ay = t / (TX + 2);
             const int gx = wrapi(x0 + ax - 1, A.nx), gy = y0 + ay - 1;
+            const int yy = (A.walls && (gy < 0 || gy >= A.ny)) ? 0 : wrapi(gy, A.ny);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) rn[j][k] = A.rdev_next[didx(A, k, gx, yy)];
+        }
+#pragma unroll
+        for (int j = 0; j < IA; ++j) {
+            const int t = (int)threadIdx.x + j * NTHREADS;
+            if (t >= NA) break;
+            const int ax = t % (TX + 2), ay = t / (TX + 2);
+            const int gy = y0 + ay - 1;
             if (A.walls && (gy < 0 || gy >= A.ny)) {
                 FT.add[0][ay][ax] = FT.add[1][ay][ax] = 0.0f;
                 continue;
             }
-            const int yy = wrapi(gy, A.ny);
             const int qx = ax + FH - 1, qy = ay + FH - 1;  // the node in the staged tile
             auto q = [&](int k, int d, int dx, int dy) { return FT.q[k][d][qy + dy][qx + dx]; };
             auto r = [&](int k, int d, int dx, int dy) { return FT.r[k][d][qy + dy][qx + dx]; };
 #pragma unroll
             for (int k = 0; k < 2; ++k)
-                FT.add[k][ay][ax] =
-                    force_add(A, k, q, r, A.rho_ref[k] + A.rdev_next[didx(A, k, gx, yy)]);
+                FT.add[k][ay][ax] = force_add(A, k, q, r, A.rho_ref[k] + rn[j][k]);
         }
     }
     __syncthreads();
